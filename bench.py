@@ -1,0 +1,169 @@
+"""Benchmark of the fused LB + field step on one MI355X.
+
+Workload (default): the 2D local-equilibrium wake, 2048 x 512 nodes,
+delta = lambda_p/64, FP32 populations with FP64 closure recovery, mu = 1e-2,
+bi-Gaussian driver (sigma_z = 1, sigma_x = 0.5, n_b/n0 = 1), 8000 steps. One
+"step" is one pass of the whole hot path over the grid: streaming, moments,
+recovery, forcing, collision and the Yee field update, i.e. one fused kernel
+launch. Inputs are synthetic (uniform plasma, analytic bunch) and resident in
+HBM before the timed region.
+
+Prints one JSON line: MLUPS of the whole job, the HBM roofline of the fused
+kernel (algorithmic bytes per lattice update over its HIP-event-measured
+average duration) and the CPU oracle timed on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per lattice update of the fused step: every population
+# read once and written once, the three Yee arrays (FP64) read once and
+# written once, the warm closure's lagged values read and written in place.
+def bytes_per_lu(dims, closure, storage):
+    K = (1 + dims) if closure == "lec" else (4 if dims == 1 else 8)
+    Q = 3 if dims == 1 else 9
+    sb = {"fp64": 8, "fp32": 4, "fp16dev": 2}[storage]
+    nf = 1 if dims == 1 else 3
+    nlag = 0 if closure == "lec" else (3 if dims == 1 else 5)
+    return 2 * K * Q * sb + 2 * nf * 8 + 2 * nlag * 8
+
+
+# Measured once on the GPU machine with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on
+# the fused kernel of this workload (see profiles/); None until measured or
+# after the kernel changed.
+TRAFFIC_BYTES_PER_LAUNCH = {}
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The CPU oracle (test infrastructure, FP64) on a bounded sample of the
+    same workload: the full grid for as many steps as fit the budget."""
+    import oracle
+
+    o = oracle.Oracle(w["dims"], w["nz"], w["nx"], delta=w["delta"], dt=w["dt"],
+                      tau_tilde=w["tau_tilde"], closure=0 if w["closure"] == "lec" else 1,
+                      dvel=w["dvel"], mu=w["mu"], alpha=w["alpha"], sigma_z=w["sigma_z"],
+                      sigma_x=w["sigma_x"], z0=w["z0"])
+    o.init()
+    o.step(1)  # first touch of the arrays
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        o.step(1)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    cells = w["nz"] * w["nx"]
+    return {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"full {w['nx']}x{w['nz']} grid, {n} FP64 steps ({dt:.1f} s) of the same workload"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="wake2d_lec_fp32")
+    ap.add_argument("--storage", default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the scheme is built and measured per GPU); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2309_04872_amd import workloads
+    from paper_2309_04872_amd.sim import Sim
+
+    over = {"storage": args.storage} if args.storage else {}
+    w = workloads.workload(args.workload, **over)
+    steps = args.steps if args.steps is not None else w["steps"]
+    cells = w["nz"] * w["nx"]
+
+    def build():
+        s = Sim(w["dims"], w["nz"], w["nx"], delta=w["delta"], dt=w["dt"], tau_tilde=w["tau_tilde"],
+                closure=w["closure"], dvel=w["dvel"], storage=w["storage"])
+        s.init_plasma(w["mu"], n=workloads.initial_density(w) if w.get("noise") else None)
+        s.init_driver(w["alpha"], w["sigma_z"], w["sigma_x"], z0=w["z0"])
+        return s
+
+    s = build()
+    if args.warmup:
+        s.step(args.warmup)
+    torch.cuda.synchronize()
+    # timed region: the workload from t = 0, inputs resident in HBM
+    s.init_plasma(w["mu"], n=workloads.initial_density(w) if w.get("noise") else None)
+    s.init_driver(w["alpha"], w["sigma_z"], w["sigma_x"], z0=w["z0"])
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s.stream)
+    t0 = time.perf_counter()
+    s.step(steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    dg = s.diagnostics()
+    # kernel duration: same workload again with an event pair around every launch
+    s.init_plasma(w["mu"], n=workloads.initial_density(w) if w.get("noise") else None)
+    s.init_driver(w["alpha"], w["sigma_z"], w["sigma_x"], z0=w["z0"])
+    s.set_timing(True)
+    s.step(steps)
+    k_ms, k_n = s.get_timing()
+    s.set_timing(False)
+    k_avg_s = k_ms / max(k_n, 1) / 1e3
+    blu = bytes_per_lu(w["dims"], w["closure"], w["storage"])
+    achieved = blu * cells / k_avg_s / 1e9
+    traffic = TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, w["storage"]))
+    mlups = cells * steps / (ms_total / 1e3) / 1e6
+    line = {
+        "metric": "MLUPS (LB+field)",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_total / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16"}[w["storage"]],
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload, "nz": w["nz"], "nx": w["nx"], "closure": w["closure"],
+            "populations": w["storage"], "recovery": "f64", "steps_per_run": steps,
+            "delta": "lambda_p/%d" % round(2 * np.pi / w["delta"]), "mu": w["mu"],
+            "alpha": w["alpha"], "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_step2d" if w["dims"] == 2 else "k_step1d",
+            "kernel_avg_us": k_avg_s * 1e6, "bytes_per_lu": blu, "launches": k_n,
+        },
+        "wall_s": wall,
+        "diagnostics": {"sum_n": dg[0], "field_energy": dg[1], "max_lattice_mach": dg[4]},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * lbwake.h -- C ABI of the MI355X library for the moment-matching lattice
+ * Boltzmann (LB) scheme for warm relativistic plasma wakes of Simeoni et al.,
+ * "Lattice Boltzmann method for warm fluid simulations of plasma wakefield
+ * acceleration" (arXiv 2309.04872).
+ *
+ * The calls follow the paper's statement of the problem (Sec. 5): a plasma of
+ * ion density n_i = 1 at initial temperature mu, a rigid bi-Gaussian driver
+ * bunch moving at c (eq. bunch-density), a domain and resolution; initialise
+ * the plasma and the driver, advance N time steps, read moments and fields.
+ *
+ * Units: plasma units, c = m_e = e = 1, n_i = 1, electrons carry charge -1;
+ * time in 1/omega_p, length in 1/k_p, E in m_e c omega_p / e, B in E / c.
+ *
+ * Grid: node (j, i) sits at z_i = i*delta, x_j = (j - (nx-1)/2)*delta. Every
+ * host array is [nx][nz] doubles with z fastest (nx = 1 in 1D). In 2D the
+ * fields live on a Yee grid: E_z at (z_{i+1/2}, x_j), E_x at (z_i, x_{j+1/2}),
+ * B_y at (z_{i+1/2}, x_{j+1/2}); with open boundaries the last half-integer
+ * slot along a staggered direction is a copy ghost.
+ *
+ * One time step (Sec. 2.1 eq. lbe, Sec. 2.2, Sec. 3.1 / 4.1, Sec. 5):
+ *   zeroth moments A_k = sum_i f_{k,i}; closure recovery of n, u (and theta);
+ *   forcing F_k from gradients of the recovered fields and the Lorentz force
+ *   of E^n, B^n; BGK relaxation toward the moment-matching equilibrium plus
+ *   S_i = w_i F_k; streaming (open copy or periodic boundaries); Yee update of
+ *   E, B with the plasma current -n u and the driver current -n_b z^.
+ *
+ * Ownership: the caller owns the device workspace (e.g. a torch tensor of
+ * lbw_workspace_bytes() bytes) and the HIP stream, and keeps both alive for
+ * the lifetime of the lbw_sim; the library never allocates device memory.
+ * Host buffers passed in are read during the call only.
+ *
+ * Errors: every call returns an lbw_status; the message of the last failure
+ * is available from lbw_last_error(). Calls on one lbw_sim are not
+ * thread-safe; different lbw_sim objects on different streams are
+ * independent.
+ */
+#ifndef LBWAKE_H
+#define LBWAKE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBW_OK = 0,
+    LBW_ERR_ARG = -1,        /* invalid argument or size mismatch */
+    LBW_ERR_WORKSPACE = -2,  /* workspace missing, too small or misaligned */
+    LBW_ERR_HIP = -3,        /* a HIP call failed */
+    LBW_ERR_UNSTABLE = -4,   /* tau~ <= 1/2 or Courant number too large */
+    LBW_ERR_NONFINITE = -5,  /* NaN or Inf found in the state */
+    LBW_ERR_STATE = -6,      /* call out of order (e.g. step before init) */
+    LBW_ERR_UNSUPPORTED = -7 /* valid request this build does not implement */
+} lbw_status;
+
+typedef enum { LBW_LEC = 0, LBW_WARMC = 1 } lbw_closure;
+/* Population storage: FP64; FP32 (FP64 recovery); FP16 deviations
+ * g = f - w_i A_ref with FP32 arithmetic (FP64 recovery). */
+typedef enum { LBW_FP64 = 0, LBW_FP32 = 1, LBW_FP16DEV = 2 } lbw_storage;
+typedef enum { LBW_BC_OPEN = 0, LBW_BC_PERIODIC = 1 } lbw_bc;
+
+/* Fluid observables for lbw_read_moment (one value per node). */
+typedef enum {
+    LBW_N = 0,      /* lab-frame electron density n */
+    LBW_UZ = 1,     /* transport velocity u_z */
+    LBW_UX = 2,     /* transport velocity u_x (0 in 1D) */
+    LBW_GAMMA = 3,  /* Lorentz factor of u */
+    LBW_N0 = 4,     /* rest-frame density n / gamma */
+    LBW_P0 = 5,     /* LEC: mu n0^{1+2/D}; WARMC: P_perp = theta^{yy} */
+    LBW_LAMBDA = 6, /* WARMC lambda = n / h */
+    LBW_THZZ = 7, LBW_THXX = 8, LBW_THYY = 9, LBW_THXZ = 10, /* WARMC theta */
+    LBW_PPAR = 11,  /* rest-frame longitudinal pressure (LEC: = P0) */
+    LBW_MZ = 12,    /* momentum density n gamma u_z */
+    LBW_MX = 13,
+    LBW_NMOMENTS = 14
+} lbw_moment;
+
+/* Fields for lbw_read_field. */
+typedef enum {
+    LBW_EZ = 0, LBW_EX = 1, LBW_BY = 2,
+    LBW_WAKE_X = 3, /* transverse wakefield E_x - B_y (nodes only) */
+    LBW_NFIELDS = 4
+} lbw_field;
+
+typedef struct {
+    int dims;          /* 1 (D1Q3 stencil) or 2 (D2Q9 stencil, Yee TM fields) */
+    int nz, nx;        /* nodes along z and x; nx = 1 in 1D */
+    double delta;      /* cell size */
+    double dt;         /* time step */
+    double tau_tilde;  /* BGK relaxation time over dt, must exceed 1/2 */
+    int closure;       /* lbw_closure */
+    double dvel;       /* D, dimension of the kinetic momentum space: 1 or 3 */
+    int storage;       /* lbw_storage */
+    int bc_z, bc_x;    /* lbw_bc */
+} lbw_grid_desc;
+
+typedef struct {
+    double mu;             /* k_B T_i / (m c^2) */
+    const double *n_init;  /* nullable [nx][nz] initial density (default 1) */
+    const double *uz_init; /* nullable initial velocity u_z (default 0) */
+    const double *ux_init; /* nullable initial velocity u_x (default 0) */
+} lbw_plasma_desc;
+
+typedef struct {
+    double alpha;      /* peak bunch density n_b / n_i */
+    double sigma_z;    /* rms length */
+    double sigma_x;    /* rms width (ignored in 1D) */
+    double z0, x0;     /* initial centre */
+    int nslices;       /* 0: Gaussian; else piecewise-constant slice weights */
+    const double *slice_w;         /* nslices weights (copied) */
+    double slice_zmin, slice_zmax; /* slice span in zeta = z - z0 - t */
+} lbw_driver_desc;
+
+typedef struct lbw_sim lbw_sim;
+
+/* Bytes of device workspace a simulation of this grid needs (0 if the
+ * descriptor is invalid). The workspace must be 256-byte aligned. */
+size_t lbw_workspace_bytes(const lbw_grid_desc *grid);
+
+/* Validate the grid (tau~ > 1/2, Courant dt <= delta / sqrt(dims)) and bind
+ * the caller's workspace and stream (hipStream_t, NULL = default stream). */
+lbw_status lbw_create(const lbw_grid_desc *grid, void *device_workspace,
+                      size_t workspace_bytes, void *hip_stream, lbw_sim **out);
+
+/* Plasma at equilibrium (Sec. 2: f_i = f_eq_i(A_k, u) of the initial fluid;
+ * the warm closure starts from the boosted rest state, eq. traces3 and
+ * eq. double-boost). Resets fields to zero, the driver to none and the step
+ * counter to 0. Host arrays are [nx][nz]. */
+lbw_status lbw_init_plasma(lbw_sim *sim, const lbw_plasma_desc *plasma);
+
+/* Equilibrium populations of arbitrary advected scalars A[K][nx][nz]
+ * (K = 2/4 in 1D, 3/8 in 2D for LEC/WARMC, in the order of the paper's
+ * advected vectors) moving at u; fields zero; mu as given. */
+lbw_status lbw_init_moments(lbw_sim *sim, double mu, const double *A,
+                            const double *uz, const double *ux);
+
+/* Rigid driver (eq. bunch-density with rms widths). init_fields = 1 also sets
+ * E, B to the field of the bunch alone at t = 0 (Sec. 5): 1D the causal
+ * Gauss-consistent E_z, 2D the vacuum solution travelling at c. */
+lbw_status lbw_init_driver(lbw_sim *sim, const lbw_driver_desc *driver,
+                           int init_fields);
+
+/* Overwrite a raw Yee array (LBW_EZ, LBW_EX: E^n; LBW_BY: B^{n-1/2}). */
+lbw_status lbw_set_field(lbw_sim *sim, int which, const double *host, size_t count);
+
+/* Advance nsteps time steps (asynchronous on the stream). */
+lbw_status lbw_step(lbw_sim *sim, int nsteps);
+
+/* Recover one fluid observable at every node into host_out (count =
+ * nx*nz doubles); synchronises the stream. */
+lbw_status lbw_read_moment(lbw_sim *sim, int which, double *host_out, size_t count);
+
+/* Same into a device buffer of nx*nz doubles, asynchronous on the stream. */
+lbw_status lbw_read_moment_device(lbw_sim *sim, int which, double *device_out);
+
+/* Fields: at_nodes = 1 gives node averages of E^n and B^n; at_nodes = 0 the
+ * raw Yee arrays E^n, B^{n-1/2} (ghost slots reported as their copies). */
+lbw_status lbw_read_field(lbw_sim *sim, int which, int at_nodes, double *host_out,
+                          size_t count);
+
+/* out[8]: sum n dV; field energy; kinetic energy sum n (gamma - 1) dV; rms
+ * Gauss residual div E - (1 - n - n_b); max |u| / (delta / dt); number of
+ * non-finite nodes; LEC recovery fallbacks so far; step count. Reductions in
+ * FP64. Returns LBW_ERR_NONFINITE when out[5] > 0. */
+lbw_status lbw_diagnostics(lbw_sim *sim, double *out);
+
+long lbw_step_count(const lbw_sim *sim);
+
+/* Kernel timing: while enabled, lbw_step brackets every fused step launch
+ * with a pair of HIP events on the simulation's stream; lbw_get_timing
+ * returns the summed kernel time (ms) and the number of launches since the
+ * last enable (it synchronises the stream). Off by default. */
+lbw_status lbw_set_timing(lbw_sim *sim, int enable);
+lbw_status lbw_get_timing(lbw_sim *sim, double *kernel_ms, long *launches);
+
+/* Checkpoint: populations, fields, lagged values, step counter. */
+size_t lbw_state_bytes(const lbw_sim *sim);
+lbw_status lbw_save_state(lbw_sim *sim, void *host, size_t bytes);
+lbw_status lbw_load_state(lbw_sim *sim, const void *host, size_t bytes);
+
+const char *lbw_last_error(const lbw_sim *sim);
+const char *lbw_version(void);
+
+/* Releases the handle; the workspace and stream stay the caller's. */
+void lbw_destroy(lbw_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,40 @@
+"""Build the HIP library ``liblbwake.so`` for gfx950 with hipcc (in-tree)."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "csrc", "lbwake.hip")
+DEPS = [SRC, os.path.join(HERE, "csrc", "lbw_kernels.hpp"), os.path.join(HERE, "csrc", "lbw_device.hpp"),
+        os.path.join(ROOT, "include", "lbwake.h")]
+SO = os.path.join(HERE, "liblbwake.so")
+ARCH = os.environ.get("LBW_OFFLOAD_ARCH", "gfx950")
+
+HIPCC_FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    # packed FP32 instructions stay off (they have given wrong results on this hardware)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-lambda-capture",
+]
+
+
+def build(force: bool = True, verbose: bool = False) -> str:
+    """Compile ``csrc/lbwake.hip`` into ``liblbwake.so``; always recompiles when force."""
+    if not force and os.path.exists(SO) and all(os.path.getmtime(SO) >= os.path.getmtime(d) for d in DEPS):
+        return SO
+    tmp = SO + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SO)
+    return SO
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    print(SO)
+    sys.exit(0)

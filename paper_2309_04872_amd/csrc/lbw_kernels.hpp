@@ -1,0 +1,753 @@
+// lbw_kernels.hpp -- fused time-step kernels of the moment-matching LB scheme
+// for warm relativistic plasma wakes (Simeoni et al., arXiv 2309.04872), plus
+// the small kernels around them (finish, init, read-out, diagnostics).
+//
+// Time levels. The state between two fused launches is (f*^{n-1}, E^{n-1},
+// B^{n-3/2}, lag^{n-1}): launch n pulls f^n (streaming, Sec. 2.1), recovers
+// n^n, u^n (Sec. 3.1 / 4.1), completes the Yee update of step n-1 with the
+// current J^n = -n^n u^n (E^{n-1} -> E^n, B^{n-3/2} -> B^{n-1/2}), forms
+// B^n = B^{n-1/2} - dt/2 curl E^n, the forcing F^n and collides (eq. lbe,
+// eq. ade-feq, S_i = w_i F) into f*^n. A canonical state (f^n post-stream,
+// E^n, B^{n-1/2}) enters with do_pull = do_maxwell = 0.
+#pragma once
+
+#include "lbw_device.hpp"
+
+namespace lbw {
+
+constexpr int NLAG2 = 5;  // theta^00, theta^0z, theta^0x, lambda u_z, lambda u_x
+constexpr int NLAG1 = 3;  // theta^00, theta^0z, lambda u_z
+
+struct StepArgs {
+    const void *src;   // populations in: f*^{n-1} (pull) or canonical f^n
+    void *dst;         // populations out: f*^n
+    const double *ez_in, *ex_in, *by_in;
+    double *ez_out, *ex_out, *by_out;
+    double *lag;                 // warm closure lagged values, [NLAG][ncell], in place
+    unsigned int *fallbacks;     // LEC recovery fallback counter
+    const double *aref;          // per-scalar storage reference A_ref (device, K values)
+    int nz, nx, ncell;
+    int bcz, bcx;
+    double delta, dt, inv2d, omega, lam, mu, a_lec, two_over_d;
+    int dcode;                   // 1, 3 or 0 (general D)
+    int do_pull, do_maxwell, lag_init;
+    long step;
+    Driver drv;
+};
+
+// ---------------------------------------------------------------------------
+// Collision of one scalar in deviation form (A_ref = 0 gives the plain form):
+// s*_q = (1 - omega) s_q + omega w_q (dA + A P_q) + dt w_q F,
+// P_q = 3 (e_q.u)/Lambda + 9/2 (e_q.u)^2/Lambda^2 - 3/2 u^2/Lambda^2, which is
+// f_eq_q / (w_q A) - 1 of eq. ade-feq with nu^2 = Lambda^2 / 3.
+template <int DIM, class CT>
+__device__ __forceinline__ void collide_scalar(CT *s, CT dA, CT A, CT uz, CT ux, CT c1, CT c2,
+                                               CT c3uu, CT omega, CT dtF)
+{
+    using L = Lattice<DIM>;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+        const CT w = (CT)L::w(q);
+        const CT eu = uz * (CT)L::ez(q) + ux * (CT)L::ex(q);
+        const CT P = c1 * eu + c2 * eu * eu - c3uu;
+        s[q] = ((CT)1 - omega) * s[q] + omega * w * (dA + A * P) + w * dtF;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D fused step. Tile TZ x TX nodes per workgroup (one node per thread);
+// recovery on the tile plus a one-node ring (LDS), fields on a two-node halo.
+template <int CL, class ST, int TZ, int TX>
+__global__ __launch_bounds__(TZ *TX) void k_step2d(StepArgs a)
+{
+    using L = Lattice<2>;
+    using CT = typename Store<ST>::ct;
+    constexpr int Q = L::Q;
+    constexpr int K = NScal<2, CL>::K;
+    constexpr int NT = TZ * TX;
+    constexpr int RZ = TZ + 2, RX = TX + 2;  // recovery region (ring of 1)
+    constexpr int FZ = TZ + 4, FX = TX + 4;  // field region (halo of 2)
+    constexpr int NG = CL == LEC ? 1 : 7;    // gradient quantities
+    constexpr int NRING = 2 * RZ + 2 * TX;
+
+    __shared__ double s_ez[FX][FZ], s_ex[FX][FZ], s_by[FX][FZ], s_bn[FX][FZ];
+    __shared__ double s_jz[RX][RZ], s_jx[RX][RZ];
+    __shared__ double s_g[NG][RX][RZ];
+
+    const int tid = threadIdx.x;
+    const int nz = a.nz, nx = a.nx, bcz = a.bcz, bcx = a.bcx;
+    const size_t nc = (size_t)a.ncell;
+    const int z0 = blockIdx.x * TZ, x0 = blockIdx.y * TX;
+    const ST *src = (const ST *)a.src;
+    ST *dst = (ST *)a.dst;
+
+    // local coordinates of a global (unwrapped) coordinate after the boundary rule
+    auto fzn = [&](int g) { return map_node(g, nz, bcz) - (z0 - 2); };
+    auto fzs = [&](int g) { return map_stag(g, nz, bcz) - (z0 - 2); };
+    auto fxn = [&](int g) { return map_node(g, nx, bcx) - (x0 - 2); };
+    auto fxs = [&](int g) { return map_stag(g, nx, bcx) - (x0 - 2); };
+    auto rzn = [&](int g) { return map_node(g, nz, bcz) - (z0 - 1); };
+    auto rxn = [&](int g) { return map_node(g, nx, bcx) - (x0 - 1); };
+
+    // ---- 1. old fields into LDS (E^{n-1}, B^{n-3/2}; or E^n, B^{n-1/2})
+    for (int p = tid; p < FZ * FX; p += NT) {
+        const int fz = p % FZ, fx = p / FZ;
+        const int gz = z0 - 2 + fz, gx = x0 - 2 + fx;
+        s_ez[fx][fz] = a.ez_in[(size_t)fix_node(gx, nx, bcx) * nz + fix_stag(gz, nz, bcz)];
+        s_ex[fx][fz] = a.ex_in[(size_t)fix_stag(gx, nx, bcx) * nz + fix_node(gz, nz, bcz)];
+        s_by[fx][fz] = a.by_in[(size_t)fix_stag(gx, nx, bcx) * nz + fix_stag(gz, nz, bcz)];
+    }
+
+    const double two_over_d = a.two_over_d, a_lec = a.a_lec;
+    double aref[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) aref[k] = a.aref[k];
+
+    // pull the K x Q populations of node (gz, gx) and return the FP64 moments
+    auto pull = [&](int gz, int gx, CT (*s)[Q], double *A) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int sz = a.do_pull ? gz - L::ez(q) : gz;
+            const int sx = a.do_pull ? gx - L::ex(q) : gx;
+            const size_t c = (size_t)fix_node(sx, nx, bcx) * nz + fix_node(sz, nz, bcz);
+#pragma unroll
+            for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src, (size_t)(k * Q + q) * nc + c);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            CT acc = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc += s[k][q];
+            A[k] = aref[k] + (double)acc;
+        }
+    };
+
+    // recovery of one node into the LDS ring/tile slot (rz, rx)
+    auto recover_to_lds = [&](const double *A, int rz, int rx, double &uz, double &ux) {
+        const double n = A[0];
+        if constexpr (CL == LEC) {
+            LecRec r;
+            if (!lec_recover(n, A[1], A[2], a_lec, a.dcode, two_over_d, r)) {
+                if (a.fallbacks) atomicAdd(a.fallbacks, 1u);
+            }
+            uz = r.uz;
+            ux = r.ux;
+            s_g[0][rx][rz] = r.phi;
+        } else {
+            WarmRec r;
+            warm_recover<2>(A, r);
+            uz = r.uz;
+            ux = r.ux;
+            s_g[0][rx][rz] = r.th0z;
+            s_g[1][rx][rz] = r.th0x;
+            s_g[2][rx][rz] = r.thzz;
+            s_g[3][rx][rz] = r.thxx;
+            s_g[4][rx][rz] = r.thxz;
+            s_g[5][rx][rz] = r.luz;
+            s_g[6][rx][rz] = r.lux;
+        }
+        s_jz[rx][rz] = -n * uz;
+        s_jx[rx][rz] = -n * ux;
+    };
+
+    // ---- 2. ring nodes: pull, recover, keep only the LDS results
+    if (tid < NRING) {
+        int rz, rx;
+        if (tid < RZ) { rz = tid; rx = 0; }
+        else if (tid < 2 * RZ) { rz = tid - RZ; rx = RX - 1; }
+        else { const int s = tid - 2 * RZ; rx = 1 + s / 2; rz = (s & 1) ? RZ - 1 : 0; }
+        CT sr[K][Q];
+        double Ar[K];
+        pull(z0 - 1 + rz, x0 - 1 + rx, sr, Ar);
+        double uzr, uxr;
+        recover_to_lds(Ar, rz, rx, uzr, uxr);
+    }
+
+    // ---- 3. own node: pull, recover, keep populations in registers
+    const int lz = tid % TZ, lx = tid / TZ;
+    const int gz = z0 + lz, gx = x0 + lx;
+    const bool active = gz < nz && gx < nx;
+    CT s[K][Q];
+    double A[K];
+    pull(gz, gx, s, A);
+    double uz, ux;
+    recover_to_lds(A, lz + 1, lx + 1, uz, ux);
+    __syncthreads();
+
+    const double dt = a.dt, hdt = 0.5 * a.dt, id = 1.0 / a.delta;
+    // ---- 4. finish the Yee update of the previous step with J^n
+    if (a.do_maxwell) {
+        for (int p = tid; p < (FZ - 1) * (FX - 1); p += NT) {
+            const int fz = p % (FZ - 1), fx = p / (FZ - 1);
+            const int gzz = z0 - 2 + fz, gxx = x0 - 2 + fx;
+            const double curl = ((s_ex[fxs(gxx)][fzn(gzz + 1)] - s_ex[fxs(gxx)][fzn(gzz)]) -
+                                 (s_ez[fxn(gxx + 1)][fzs(gzz)] - s_ez[fxn(gxx)][fzs(gzz)])) * id;
+            const double b1 = s_by[fx][fz] - hdt * curl;  // B^{n-1}
+            s_by[fx][fz] = b1 - hdt * curl;               // B^{n-1/2}
+        }
+        __syncthreads();
+        const double th = (a.step - 0.5) * dt;
+        for (int p = tid; p < (FZ - 2) * (FX - 2); p += NT) {
+            const int fz = 1 + p % (FZ - 2), fx = 1 + p / (FZ - 2);
+            const int gzz = z0 - 2 + fz, gxx = x0 - 2 + fx;
+            if (fx <= FX - 3) {  // E_x at (z_gzz, x_{gxx+1/2})
+                const double jx = 0.5 * (s_jx[rxn(gxx)][rzn(gzz)] + s_jx[rxn(gxx + 1)][rzn(gzz)]);
+                const double cx = -(s_by[fxs(gxx)][fzs(gzz)] - s_by[fxs(gxx)][fzs(gzz - 1)]) * id;
+                s_ex[fx][fz] = s_ex[fx][fz] + dt * (cx - jx);
+            }
+            if (fz <= FZ - 3) {  // E_z at (z_{gzz+1/2}, x_gxx)
+                const double jz = 0.5 * (s_jz[rxn(gxx)][rzn(gzz)] + s_jz[rxn(gxx)][rzn(gzz + 1)]);
+                const double jb = -driver_density<2>(a.drv, (gzz + 0.5) * a.delta,
+                                                     (gxx - 0.5 * (nx - 1)) * a.delta, th);
+                const double cz = (s_by[fxs(gxx)][fzs(gzz)] - s_by[fxs(gxx - 1)][fzs(gzz)]) * id;
+                s_ez[fx][fz] = s_ez[fx][fz] + dt * (cz - jz - jb);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- 5. B^n = B^{n-1/2} - dt/2 curl E^n around the tile; write E^n, B^{n-1/2}
+    for (int p = tid; p < (FZ - 3) * (FX - 3); p += NT) {
+        const int fz = 1 + p % (FZ - 3), fx = 1 + p / (FZ - 3);
+        const int gzz = z0 - 2 + fz, gxx = x0 - 2 + fx;
+        const double curl = ((s_ex[fxs(gxx)][fzn(gzz + 1)] - s_ex[fxs(gxx)][fzn(gzz)]) -
+                             (s_ez[fxn(gxx + 1)][fzs(gzz)] - s_ez[fxn(gxx)][fzs(gzz)])) * id;
+        s_bn[fx][fz] = s_by[fx][fz] - hdt * curl;
+    }
+    if (active) {
+        const size_t c = (size_t)gx * nz + gz;
+        a.ez_out[c] = s_ez[lx + 2][lz + 2];
+        a.ex_out[c] = s_ex[lx + 2][lz + 2];
+        a.by_out[c] = s_by[lx + 2][lz + 2];
+    }
+    __syncthreads();
+    if (!active) return;
+
+    // ---- 6. node fields, forcing, collision
+    const double Ez = 0.5 * (s_ez[fxn(gx)][fzs(gz - 1)] + s_ez[fxn(gx)][fzs(gz)]);
+    const double Ex = 0.5 * (s_ex[fxs(gx - 1)][fzn(gz)] + s_ex[fxs(gx)][fzn(gz)]);
+    const double By = 0.25 * (s_bn[fxs(gx)][fzs(gz)] + s_bn[fxs(gx)][fzs(gz - 1)] +
+                              s_bn[fxs(gx - 1)][fzs(gz)] + s_bn[fxs(gx - 1)][fzs(gz - 1)]);
+    const int rzc = lz + 1, rxc = lx + 1;
+    const int rzp = rzn(gz + 1), rzm = rzn(gz - 1), rxp = rxn(gx + 1), rxm = rxn(gx - 1);
+    auto Dz = [&](int g) { return (s_g[g][rxc][rzp] - s_g[g][rxc][rzm]) * a.inv2d; };
+    auto Dx = [&](int g) { return (s_g[g][rxp][rzc] - s_g[g][rxm][rzc]) * a.inv2d; };
+    const double n = A[0];
+    double F[K];
+    const size_t c = (size_t)gx * nz + gz;
+    if constexpr (CL == LEC) {
+        // eq. lb-ade-lec-comps-F (q = -1): F = -mu grad n0^{1+2/D} - n (E + u x B)
+        F[0] = 0.0;
+        F[1] = -a.mu * Dz(0) - n * (Ez + ux * By);
+        F[2] = -a.mu * Dx(0) - n * (Ex - uz * By);
+    } else {
+        // App. A warm-closure right-hand sides, Cartesian slab (r -> x, phi -> y)
+        const double th0z = s_g[0][rxc][rzc], th0x = s_g[1][rxc][rzc];
+        const double thzz = s_g[2][rxc][rzc], thxx = s_g[3][rxc][rzc];
+        const double thxz = s_g[4][rxc][rzc];
+        const double luz = s_g[5][rxc][rzc], lux = s_g[6][rxc][rzc];
+        const double th00 = ux * th0x + uz * th0z;
+        double l00, l0z, l0x, lluz, llux;
+        if (a.lag_init) {
+            l00 = th00; l0z = th0z; l0x = th0x; lluz = luz; llux = lux;
+        } else {
+            l00 = a.lag[0 * nc + c]; l0z = a.lag[1 * nc + c]; l0x = a.lag[2 * nc + c];
+            lluz = a.lag[3 * nc + c]; llux = a.lag[4 * nc + c];
+        }
+        a.lag[0 * nc + c] = th00; a.lag[1 * nc + c] = th0z; a.lag[2 * nc + c] = th0x;
+        a.lag[3 * nc + c] = luz; a.lag[4 * nc + c] = lux;
+        const double idt = 1.0 / dt;
+        const double dt00 = (th00 - l00) * idt, dt0z = (th0z - l0z) * idt, dt0x = (th0x - l0x) * idt;
+        const double dtluz = (luz - lluz) * idt, dtlux = (lux - llux) * idt;
+        F[0] = 0.0;
+        F[1] = -dt00 - Dx(1) - Dz(0) - n * (Ex * ux + Ez * uz);
+        F[2] = -dt0z - Dx(4) - Dz(2) - n * (Ez + ux * By);
+        F[3] = -dt0x - Dx(3) - Dz(4) - n * (Ex - uz * By);
+        F[4] = -2.0 * th0z * dtluz - 2.0 * thxz * Dx(5) - 2.0 * thzz * Dz(5) -
+               2.0 * (Ez * th0z + By * thxz);
+        F[5] = -2.0 * th0x * dtlux - 2.0 * thxx * Dx(6) - 2.0 * thxz * Dz(6) -
+               2.0 * (Ex * th0x - By * thxz);
+        F[6] = 0.0;
+        F[7] = -th0z * dtlux - th0x * dtluz - thxz * Dx(6) - thxx * Dx(5) - thzz * Dz(6) -
+               thxz * Dz(5) - (Ex * th0z + Ez * th0x + By * (thxx - thzz));
+    }
+    const CT lam = (CT)a.lam;
+    const CT c1 = (CT)3 / lam, c2 = (CT)4.5 / (lam * lam);
+    const CT c3uu = (CT)(1.5 * (uz * uz + ux * ux) / (a.lam * a.lam));
+    const CT om = (CT)a.omega;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        collide_scalar<2, CT>(s[k], (CT)(A[k] - aref[k]), (CT)A[k], (CT)uz, (CT)ux, c1, c2, c3uu,
+                              om, (CT)(dt * F[k]));
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Store<ST>::st(dst, (size_t)(k * Q + q) * nc + c, s[k][q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1D fused step: TZ nodes per workgroup plus a ring of one node on each side;
+// E_z sits on the nodes and its update is local: E^n = E^{n-1} + dt (n u + n_b).
+template <int CL, class ST, int TZ>
+__global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
+{
+    using L = Lattice<1>;
+    using CT = typename Store<ST>::ct;
+    constexpr int Q = L::Q;
+    constexpr int K = NScal<1, CL>::K;
+    constexpr int NG = CL == LEC ? 1 : 3;  // phi | theta^0z, theta^zz, lambda u_z
+    __shared__ double s_g[NG][TZ + 2];
+
+    const int tid = threadIdx.x;
+    const int nz = a.nz, bcz = a.bcz;
+    const size_t nc = (size_t)a.ncell;
+    const int z0 = blockIdx.x * TZ;
+    const ST *src = (const ST *)a.src;
+    ST *dst = (ST *)a.dst;
+    const double two_over_d = a.two_over_d, a_lec = a.a_lec;
+    double aref[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) aref[k] = a.aref[k];
+
+    auto pull = [&](int gz, CT (*s)[Q], double *A) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int sz = a.do_pull ? gz - L::ez(q) : gz;
+            const size_t c = (size_t)fix_node(sz, nz, bcz);
+#pragma unroll
+            for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src, (size_t)(k * Q + q) * nc + c);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            CT acc = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc += s[k][q];
+            A[k] = aref[k] + (double)acc;
+        }
+    };
+    struct R1 { double uz, gamma, phi; WarmRec w; };
+    auto recover = [&](const double *A, int rz, R1 &r) {
+        if constexpr (CL == LEC) {
+            LecRec l;
+            if (!lec_recover(A[0], A[1], 0.0, a_lec, a.dcode, two_over_d, l)) {
+                if (a.fallbacks) atomicAdd(a.fallbacks, 1u);
+            }
+            r.uz = l.uz;
+            r.phi = l.phi;
+            s_g[0][rz] = l.phi;
+        } else {
+            warm_recover<1>(A, r.w);
+            r.uz = r.w.uz;
+            s_g[0][rz] = r.w.th0z;
+            s_g[1][rz] = r.w.thzz;
+            s_g[2][rz] = r.w.luz;
+        }
+    };
+
+    if (tid < 2) {
+        const int rz = tid == 0 ? 0 : TZ + 1;
+        CT sr[K][Q];
+        double Ar[K];
+        pull(z0 - 1 + rz, sr, Ar);
+        R1 rr;
+        recover(Ar, rz, rr);
+    }
+    const int gz = z0 + tid;
+    const bool active = gz < nz;
+    CT s[K][Q];
+    double A[K];
+    pull(gz, s, A);
+    R1 r;
+    recover(A, tid + 1, r);
+    __syncthreads();
+    if (!active) return;
+
+    const double dt = a.dt;
+    const double n = A[0], uz = r.uz;
+    const size_t c = (size_t)gz;
+    double Ez = a.ez_in[c];
+    if (a.do_maxwell) {
+        const double jb = driver_density<1>(a.drv, gz * a.delta, 0.0, (a.step - 0.5) * dt);
+        Ez = Ez + dt * (n * uz + jb);
+    }
+    a.ez_out[c] = Ez;
+    const int rp = map_node(gz + 1, nz, bcz) - (z0 - 1), rm = map_node(gz - 1, nz, bcz) - (z0 - 1);
+    auto Dz = [&](int g) { return (s_g[g][rp] - s_g[g][rm]) * a.inv2d; };
+    double F[K];
+    if constexpr (CL == LEC) {
+        F[0] = 0.0;
+        F[1] = -a.mu * Dz(0) - n * Ez;
+    } else {
+        const double th0z = r.w.th0z, thzz = r.w.thzz, luz = r.w.luz, th00 = r.w.th00;
+        double l00, l0z, lluz;
+        if (a.lag_init) {
+            l00 = th00; l0z = th0z; lluz = luz;
+        } else {
+            l00 = a.lag[0 * nc + c]; l0z = a.lag[1 * nc + c]; lluz = a.lag[2 * nc + c];
+        }
+        a.lag[0 * nc + c] = th00; a.lag[1 * nc + c] = th0z; a.lag[2 * nc + c] = luz;
+        const double idt = 1.0 / dt;
+        F[0] = 0.0;
+        F[1] = -(th00 - l00) * idt - Dz(0) - n * (Ez * uz);
+        F[2] = -(th0z - l0z) * idt - Dz(1) - n * Ez;
+        F[3] = -2.0 * th0z * ((luz - lluz) * idt) - 2.0 * thzz * Dz(2) - 2.0 * (Ez * th0z);
+    }
+    const CT lam = (CT)a.lam;
+    const CT c1 = (CT)3 / lam, c2 = (CT)4.5 / (lam * lam);
+    const CT c3uu = (CT)(1.5 * uz * uz / (a.lam * a.lam));
+    const CT om = (CT)a.omega;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        collide_scalar<1, CT>(s[k], (CT)(A[k] - aref[k]), (CT)A[k], (CT)uz, (CT)0, c1, c2, c3uu,
+                              om, (CT)(dt * F[k]));
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Store<ST>::st(dst, (size_t)(k * Q + q) * nc + c, s[k][q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finish: bring a mid-step state (f*^{n-1}, E^{n-1}, B^{n-3/2}) to the
+// canonical one (f^n, E^n, B^{n-1/2}). Pass 1 streams f* into the other
+// buffer and records J^n = -n^n u^n; in 1D it also finishes E_z.
+template <int DIM, int CL, class ST>
+__global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
+{
+    using L = Lattice<DIM>;
+    constexpr int Q = L::Q;
+    constexpr int K = NScal<DIM, CL>::K;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.ncell) return;
+    const int gz = idx % a.nz, gx = idx / a.nz;
+    const size_t nc = (size_t)a.ncell;
+    const ST *src = (const ST *)a.src;
+    ST *dst = (ST *)a.dst;
+    double A[K];
+    for (int k = 0; k < K; ++k) {
+        typename Store<ST>::ct acc = 0;
+        for (int q = 0; q < Q; ++q) {
+            const int sz = gz - L::ez(q), sx = gx - L::ex(q);
+            const size_t c = (size_t)fix_node(sx, a.nx, a.bcx) * a.nz + fix_node(sz, a.nz, a.bcz);
+            const typename Store<ST>::ct v = Store<ST>::ld(src, (size_t)(k * Q + q) * nc + c);
+            Store<ST>::st(dst, (size_t)(k * Q + q) * nc + idx, v);
+            acc += v;
+        }
+        A[k] = a.aref[k] + (double)acc;
+    }
+    double uz, ux;
+    if constexpr (CL == LEC) {
+        LecRec r;
+        lec_recover(A[0], A[1], DIM == 2 ? A[K - 1] : 0.0, a.a_lec, a.dcode, a.two_over_d, r);
+        uz = r.uz;
+        ux = r.ux;
+    } else {
+        WarmRec r;
+        warm_recover<DIM>(A, r);
+        uz = r.uz;
+        ux = r.ux;
+    }
+    if (DIM == 1) {
+        const double jb = driver_density<1>(a.drv, gz * a.delta, 0.0, (a.step - 0.5) * a.dt);
+        a.ez_out[idx] = a.ez_in[idx] + a.dt * (A[0] * uz + jb);
+    } else {
+        jz[idx] = -A[0] * uz;
+        jx[idx] = -A[0] * ux;
+    }
+}
+
+// Pass 2 (2D): B^{n-1/2} = (B^{n-3/2} - dt/2 curl E^{n-1}) - dt/2 curl E^{n-1}.
+__global__ void k_finish_b2d(StepArgs a)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.ncell) return;
+    const int i = idx % a.nz, j = idx / a.nz;
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    auto EZ = [&](int jj, int ii) { return a.ez_in[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    auto EX = [&](int jj, int ii) { return a.ex_in[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
+    const double hdt = 0.5 * a.dt, id = 1.0 / a.delta;
+    const double curl = ((EX(j, i + 1) - EX(j, i)) - (EZ(j + 1, i) - EZ(j, i))) * id;
+    const double b1 = a.by_in[idx] - hdt * curl;
+    a.by_out[idx] = b1 - hdt * curl;
+}
+
+// Pass 3 (2D): E^n = E^{n-1} + dt (curl B^{n-1/2} - J^n - J_b^{n-1/2}).
+__global__ void k_finish_e2d(StepArgs a, const double *jz, const double *jx)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.ncell) return;
+    const int i = idx % a.nz, j = idx / a.nz;
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    auto BY = [&](int jj, int ii) { return a.by_out[(size_t)fix_stag(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    auto JN = [&](const double *J, int jj, int ii) { return J[(size_t)fix_node(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
+    const double dt = a.dt, id = 1.0 / a.delta;
+    const double th = (a.step - 0.5) * dt;
+    const double jxe = 0.5 * (JN(jx, j, i) + JN(jx, j + 1, i));
+    const double cx = -(BY(j, i) - BY(j, i - 1)) * id;
+    a.ex_out[idx] = a.ex_in[idx] + dt * (cx - jxe);
+    const double jze = 0.5 * (JN(jz, j, i) + JN(jz, j, i + 1));
+    const double jb = -driver_density<2>(a.drv, (i + 0.5) * a.delta, (j - 0.5 * (nx - 1)) * a.delta, th);
+    const double cz = (BY(j, i) - BY(j - 1, i)) * id;
+    a.ez_out[idx] = a.ez_in[idx] + dt * (cz - jze - jb);
+}
+
+// ---------------------------------------------------------------------------
+// Initial populations f_q = f_eq_q(A_k, u) from staged scalars A [K][ncell]
+// and velocity (uz, ux), stored as deviations from A_ref.
+template <int DIM, int CL, class ST>
+__global__ void k_init_pops(void *dst_, const double *A, const double *uzv, const double *uxv,
+                            const double *aref, int ncell, double lam)
+{
+    using L = Lattice<DIM>;
+    constexpr int Q = L::Q;
+    constexpr int K = NScal<DIM, CL>::K;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ncell) return;
+    ST *dst = (ST *)dst_;
+    const size_t nc = (size_t)ncell;
+    const double uz = uzv[idx], ux = DIM == 2 ? uxv[idx] : 0.0;
+    const double uu = uz * uz + ux * ux;
+    for (int k = 0; k < K; ++k) {
+        const double Ak = A[(size_t)k * nc + idx];
+        for (int q = 0; q < Q; ++q) {
+            const double eu = uz * L::ez(q) + ux * L::ex(q);
+            const double P = 3.0 * eu / lam + 4.5 * eu * eu / (lam * lam) - 1.5 * uu / (lam * lam);
+            const double w = L::w(q);
+            Store<ST>::st(dst, (size_t)(k * Q + q) * nc + idx,
+                          (typename Store<ST>::ct)(w * (Ak - aref[k]) + w * Ak * P));
+        }
+    }
+}
+
+// Observable at each node from canonical populations f^n.
+template <int DIM, int CL, class ST>
+__global__ void k_read_moment(StepArgs a, int which, double *out)
+{
+    using L = Lattice<DIM>;
+    constexpr int Q = L::Q;
+    constexpr int K = NScal<DIM, CL>::K;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.ncell) return;
+    const size_t nc = (size_t)a.ncell;
+    const ST *src = (const ST *)a.src;
+    double A[K];
+    for (int k = 0; k < K; ++k) {
+        typename Store<ST>::ct acc = 0;
+        for (int q = 0; q < Q; ++q) acc += Store<ST>::ld(src, (size_t)(k * Q + q) * nc + idx);
+        A[k] = a.aref[k] + (double)acc;
+    }
+    const double n = A[0];
+    double v = 0.0;
+    if constexpr (CL == LEC) {
+        LecRec r;
+        lec_recover(n, A[1], DIM == 2 ? A[K - 1] : 0.0, a.a_lec, a.dcode, a.two_over_d, r);
+        switch (which) {
+        case 0: v = n; break;
+        case 1: v = r.uz; break;
+        case 2: v = r.ux; break;
+        case 3: v = r.gamma; break;
+        case 4: v = r.n0; break;
+        case 5: case 11: v = a.mu * r.phi; break;
+        case 12: v = n * r.gamma * r.uz; break;
+        case 13: v = n * r.gamma * r.ux; break;
+        default: v = 0.0;
+        }
+    } else {
+        WarmRec r;
+        warm_recover<DIM>(A, r);
+        const double g = 1.0 / sqrt(1.0 - (r.uz * r.uz + r.ux * r.ux));
+        switch (which) {
+        case 0: v = n; break;
+        case 1: v = r.uz; break;
+        case 2: v = r.ux; break;
+        case 3: v = g; break;
+        case 4: v = n / g; break;
+        case 5: v = r.thyy; break;
+        case 6: v = r.lam; break;
+        case 7: v = r.thzz; break;
+        case 8: v = r.thxx; break;
+        case 9: v = r.thyy; break;
+        case 10: v = r.thxz; break;
+        case 11: v = warm_ppar(r); break;
+        case 12: v = n * g * r.uz; break;
+        case 13: v = n * g * r.ux; break;
+        default: v = 0.0;
+        }
+    }
+    out[idx] = v;
+}
+
+// Fields of the canonical state: raw Yee (ghost slots as copies) or node
+// averages of E^n and B^n = B^{n-1/2} - dt/2 curl E^n.
+template <int DIM>
+__global__ void k_read_field(StepArgs a, int which, int at_nodes, double *out)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.ncell) return;
+    if (DIM == 1) {
+        out[idx] = which == 0 ? a.ez_in[idx] : 0.0;
+        return;
+    }
+    const int i = idx % a.nz, j = idx / a.nz;
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    auto EZ = [&](int jj, int ii) { return a.ez_in[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    auto EX = [&](int jj, int ii) { return a.ex_in[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
+    auto BH = [&](int jj, int ii) { return a.by_in[(size_t)fix_stag(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    const double hdt = 0.5 * a.dt, id = 1.0 / a.delta;
+    auto BN = [&](int jj, int ii) {
+        const double curl = ((EX(jj, ii + 1) - EX(jj, ii)) - (EZ(jj + 1, ii) - EZ(jj, ii))) * id;
+        return BH(jj, ii) - hdt * curl;
+    };
+    double v;
+    if (!at_nodes) {
+        v = which == 0 ? EZ(j, i) : (which == 1 ? EX(j, i) : BH(j, i));
+    } else {
+        const double ez = 0.5 * (EZ(j, i - 1) + EZ(j, i));
+        const double ex = 0.5 * (EX(j - 1, i) + EX(j, i));
+        const double by = 0.25 * (BN(j, i) + BN(j, i - 1) + BN(j - 1, i) + BN(j - 1, i - 1));
+        v = which == 0 ? ez : (which == 1 ? ex : (which == 2 ? by : ex - by));
+    }
+    out[idx] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: per-block FP64 partial sums (sum n, field energy, kinetic
+// energy, Gauss residual^2, non-finite count) and maxima (|u| / Lambda),
+// combined in a fixed order by a single block.
+constexpr int NDIAG = 6;
+
+template <int DIM, int CL, class ST>
+__global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, double *part)
+{
+    using L = Lattice<DIM>;
+    constexpr int Q = L::Q;
+    constexpr int K = NScal<DIM, CL>::K;
+    __shared__ double red[NDIAG][256];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[NDIAG] = {0, 0, 0, 0, 0, 0};
+    if (idx < a.ncell) {
+        const size_t nc = (size_t)a.ncell;
+        const ST *src = (const ST *)a.src;
+        double A[K];
+        for (int k = 0; k < K; ++k) {
+            typename Store<ST>::ct acc = 0;
+            for (int q = 0; q < Q; ++q) acc += Store<ST>::ld(src, (size_t)(k * Q + q) * nc + idx);
+            A[k] = a.aref[k] + (double)acc;
+        }
+        const double n = A[0];
+        double uz, ux;
+        if constexpr (CL == LEC) {
+            LecRec r;
+            lec_recover(n, A[1], DIM == 2 ? A[K - 1] : 0.0, a.a_lec, a.dcode, a.two_over_d, r);
+            uz = r.uz;
+            ux = r.ux;
+        } else {
+            WarmRec r;
+            warm_recover<DIM>(A, r);
+            uz = r.uz;
+            ux = r.ux;
+        }
+        const double uu = uz * uz + ux * ux;
+        const double g = 1.0 / sqrt(1.0 - uu);
+        const double dV = DIM == 1 ? a.delta : a.delta * a.delta;
+        const int i = idx % a.nz, j = idx / a.nz;
+        const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+        double fe, div;
+        const double t = a.step * a.dt;
+        const double rho = 1.0 - n - driver_density<DIM>(a.drv, i * a.delta, (j - 0.5 * (nx - 1)) * a.delta, t);
+        if (DIM == 1) {
+            const double e = a.ez_in[idx];
+            fe = 0.5 * e * e * dV;
+            div = (a.ez_in[fix_node(i + 1, nz, bz)] - a.ez_in[fix_node(i - 1, nz, bz)]) * (0.5 / a.delta);
+        } else {
+            const bool rz = bz == BC_PERIODIC || i < nz - 1, rx = bx == BC_PERIODIC || j < nx - 1;
+            const double ez = a.ez_in[idx], ex = a.ex_in[idx], by = a.by_in[idx];
+            fe = ((rz ? 0.5 * ez * ez : 0.0) + (rx ? 0.5 * ex * ex : 0.0) + (rz && rx ? 0.5 * by * by : 0.0)) * dV;
+            auto EZ = [&](int jj, int ii) { return a.ez_in[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+            auto EX = [&](int jj, int ii) { return a.ex_in[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
+            div = (EZ(j, i) - EZ(j, i - 1)) / a.delta + (EX(j, i) - EX(j - 1, i)) / a.delta;
+        }
+        const bool bad = !isfinite(n) || !isfinite(uz) || !isfinite(ux) || !isfinite(a.ez_in[idx]) ||
+                         (DIM == 2 && (!isfinite(a.ex_in[idx]) || !isfinite(a.by_in[idx])));
+        v[0] = n * dV;
+        v[1] = fe;
+        v[2] = n * (g - 1.0) * dV;
+        v[3] = (div - rho) * (div - rho);
+        v[4] = bad ? 1.0 : 0.0;
+        v[5] = sqrt(uu) / a.lam;
+    }
+    for (int d = 0; d < NDIAG; ++d) red[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int sft = 128; sft > 0; sft >>= 1) {
+        if ((int)threadIdx.x < sft) {
+            for (int d = 0; d < 5; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + sft];
+            const double o = red[5][threadIdx.x + sft];
+            if (o > red[5][threadIdx.x] || o != o) red[5][threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < NDIAG; ++d) part[(size_t)d * gridDim.x + blockIdx.x] = red[d][0];
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(const double *part, int nblocks, double *out)
+{
+    __shared__ double red[NDIAG][256];
+    double v[NDIAG] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+        for (int d = 0; d < 5; ++d) v[d] += part[(size_t)d * nblocks + b];
+        const double o = part[(size_t)5 * nblocks + b];
+        if (o > v[5] || o != o) v[5] = o;
+    }
+    for (int d = 0; d < NDIAG; ++d) red[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int sft = 128; sft > 0; sft >>= 1) {
+        if ((int)threadIdx.x < sft) {
+            for (int d = 0; d < 5; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + sft];
+            const double o = red[5][threadIdx.x + sft];
+            if (o > red[5][threadIdx.x] || o != o) red[5][threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < NDIAG; ++d) out[d] = red[d][0];
+}
+
+// Analytic field of the bunch alone at t = 0 (Sec. 5). 1D: E_z(z) = alpha
+// times the integral of the profile from z to +infinity, evaluated per slice.
+// 2D: E_z = 0, E_x = -g(zeta) sigma_x sqrt(pi/2) erf(x / (sqrt 2 sigma_x)),
+// B_y = E_x taken at t = -dt/2.
+template <int DIM>
+__global__ void k_init_fields(StepArgs a, double *ez, double *ex, double *by)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.ncell) return;
+    const int i = idx % a.nz, j = idx / a.nz;
+    const Driver &d = a.drv;
+    if (DIM == 1) {
+        const double zeta = i * a.delta - d.z0;
+        const double sz = d.sigma_z, c = sz * sqrt(M_PI / 2.0), r2s = sqrt(2.0) * sz;
+        double acc;
+        if (d.nslices <= 0) {
+            acc = c * erfc(zeta / r2s);
+        } else {
+            const double h = (d.slice_zmax - d.slice_zmin) / d.nslices;
+            acc = 0.0;
+            for (int k = 0; k < d.nslices; ++k) {
+                double lo = d.slice_zmin + k * h, hi = d.slice_zmin + (k + 1) * h;
+                if (zeta >= hi) continue;
+                if (zeta > lo) lo = zeta;
+                acc += d.slice_w[k] * c * (erf(hi / r2s) - erf(lo / r2s));
+            }
+        }
+        ez[idx] = d.alpha * acc;
+        return;
+    }
+    const double xh = (j + 0.5 - 0.5 * (a.nx - 1)) * a.delta - d.x0;
+    const double sx = d.sigma_x;
+    const double tr = -sx * sqrt(M_PI / 2.0) * erf(xh / (sqrt(2.0) * sx));
+    const double ze = i * a.delta - d.z0;
+    const double zb = (i + 0.5) * a.delta - d.z0 + 0.5 * a.dt;
+    ez[idx] = 0.0;
+    ex[idx] = driver_profile(d, ze) * tr;
+    by[idx] = driver_profile(d, zb) * tr;
+}
+
+}  // namespace lbw

@@ -1,0 +1,716 @@
+// lbwake.hip -- host side of the C ABI declared in include/lbwake.h: workspace
+// layout, argument checks, launch sequencing on the caller's stream. The hot
+// path is the fused step kernel of lbw_kernels.hpp; everything here is
+// bookkeeping around it.
+#include "../../include/lbwake.h"
+#include "lbw_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbw;
+
+namespace {
+
+constexpr int TZ2 = 32, TX2 = 8;  // 2D tile (nodes along z, x)
+constexpr int TZ1 = 256;          // 1D tile
+constexpr int MAX_SLICES = 4096;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int nscalars(int dims, int closure) { return closure == LBW_LEC ? 1 + dims : (dims == 1 ? 4 : 8); }
+int nlag(int dims, int closure) { return closure == LBW_WARMC ? (dims == 1 ? NLAG1 : NLAG2) : 0; }
+size_t storage_size(int storage) { return storage == LBW_FP64 ? 8 : (storage == LBW_FP32 ? 4 : 2); }
+
+struct Layout {
+    size_t pop[2], fld[2][3], lag, stage, part, aref, slice, fallbacks, diag, total;
+    int K, Q, nblk_diag;
+};
+
+bool grid_valid(const lbw_grid_desc *g, std::string *why)
+{
+    auto bad = [&](const char *m) { if (why) *why = m; return false; };
+    if (!g) return bad("grid descriptor is NULL");
+    if (g->dims != 1 && g->dims != 2) return bad("dims must be 1 or 2");
+    if (g->nz < 4) return bad("nz must be >= 4");
+    if (g->dims == 1 && g->nx != 1) return bad("nx must be 1 in 1D");
+    if (g->dims == 2 && g->nx < 4) return bad("nx must be >= 4 in 2D");
+    if ((double)g->nz * g->nx > 2.0e9 / 72) return bad("grid too large for 32-bit plane offsets");
+    if (!(g->delta > 0) || !(g->dt > 0)) return bad("delta and dt must be positive");
+    if (g->closure != LBW_LEC && g->closure != LBW_WARMC) return bad("unknown closure");
+    if (g->storage != LBW_FP64 && g->storage != LBW_FP32 && g->storage != LBW_FP16DEV)
+        return bad("unknown storage");
+    if (g->bc_z != LBW_BC_OPEN && g->bc_z != LBW_BC_PERIODIC) return bad("unknown bc_z");
+    if (g->bc_x != LBW_BC_OPEN && g->bc_x != LBW_BC_PERIODIC) return bad("unknown bc_x");
+    if (!(g->dvel > 0)) return bad("dvel must be positive");
+    return true;
+}
+
+Layout make_layout(const lbw_grid_desc *g)
+{
+    Layout L{};
+    const size_t nc = (size_t)g->nz * g->nx;
+    L.K = nscalars(g->dims, g->closure);
+    L.Q = g->dims == 1 ? 3 : 9;
+    size_t off = 0;
+    const size_t popb = align_up(nc * L.K * L.Q * storage_size(g->storage));
+    L.pop[0] = off; off += popb;
+    L.pop[1] = off; off += popb;
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < 3; ++f) { L.fld[b][f] = off; off += align_up(nc * 8); }
+    L.lag = off; off += align_up(nc * 8 * (size_t)nlag(g->dims, g->closure));
+    const int ks = L.K > 3 ? L.K : 3;
+    L.stage = off; off += align_up(nc * 8 * (size_t)ks);
+    L.nblk_diag = (int)((nc + 255) / 256);
+    L.part = off; off += align_up((size_t)L.nblk_diag * NDIAG * 8);
+    L.aref = off; off += align_up(8 * 8);
+    L.slice = off; off += align_up(MAX_SLICES * 8);
+    L.fallbacks = off; off += align_up(8);
+    L.diag = off; off += align_up(NDIAG * 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct lbw_sim {
+    lbw_grid_desc g;
+    Layout L;
+    char *ws;
+    hipStream_t stream;
+    int pcur, fcur;
+    bool initialized, canonical, lag_valid;
+    long step;
+    double mu;
+    double aref_host[8];
+    Driver drv;
+    std::string err;
+    // kernel timing (event pairs around each fused launch)
+    bool timing;
+    std::vector<hipEvent_t> ev;
+    int ev_used;
+    double kernel_ms;
+    long launches;
+};
+
+static lbw_status fail(lbw_sim *s, lbw_status code, const std::string &m)
+{
+    if (s) s->err = m;
+    return code;
+}
+
+#define HIPCHK(sim, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((sim), LBW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel dispatch over (dims, closure, storage).
+namespace {
+
+StepArgs base_args(lbw_sim *s)
+{
+    StepArgs a{};
+    const lbw_grid_desc &g = s->g;
+    a.nz = g.nz;
+    a.nx = g.nx;
+    a.ncell = g.nz * g.nx;
+    a.bcz = g.bc_z;
+    a.bcx = g.bc_x;
+    a.delta = g.delta;
+    a.dt = g.dt;
+    a.inv2d = 1.0 / (2.0 * g.delta);
+    a.omega = 1.0 / g.tau_tilde;
+    a.lam = g.delta / g.dt;
+    a.mu = s->mu;
+    a.a_lec = (1.0 + 0.5 * g.dvel) * s->mu;
+    a.two_over_d = 2.0 / g.dvel;
+    a.dcode = g.dvel == 1.0 ? 1 : (g.dvel == 3.0 ? 3 : 0);
+    a.aref = (const double *)(s->ws + s->L.aref);
+    a.fallbacks = (unsigned int *)(s->ws + s->L.fallbacks);
+    a.lag = g.closure == LBW_WARMC ? (double *)(s->ws + s->L.lag) : nullptr;
+    a.step = s->step;
+    a.drv = s->drv;
+    return a;
+}
+
+void set_io(lbw_sim *s, StepArgs &a)
+{
+    a.src = s->ws + s->L.pop[s->pcur];
+    a.dst = s->ws + s->L.pop[1 - s->pcur];
+    a.ez_in = (const double *)(s->ws + s->L.fld[s->fcur][0]);
+    a.ex_in = (const double *)(s->ws + s->L.fld[s->fcur][1]);
+    a.by_in = (const double *)(s->ws + s->L.fld[s->fcur][2]);
+    a.ez_out = (double *)(s->ws + s->L.fld[1 - s->fcur][0]);
+    a.ex_out = (double *)(s->ws + s->L.fld[1 - s->fcur][1]);
+    a.by_out = (double *)(s->ws + s->L.fld[1 - s->fcur][2]);
+}
+
+template <int DIM, int CL, class ST> struct Impl {
+    static void step(const StepArgs &a, hipStream_t st)
+    {
+        if constexpr (DIM == 2) {
+            dim3 grid((a.nz + TZ2 - 1) / TZ2, (a.nx + TX2 - 1) / TX2);
+            hipLaunchKernelGGL((k_step2d<CL, ST, TZ2, TX2>), grid, dim3(TZ2 * TX2), 0, st, a);
+        } else {
+            dim3 grid((a.nz + TZ1 - 1) / TZ1);
+            hipLaunchKernelGGL((k_step1d<CL, ST, TZ1>), grid, dim3(TZ1), 0, st, a);
+        }
+    }
+    static void finish(const StepArgs &a, double *jz, double *jx, hipStream_t st)
+    {
+        const int nb = (a.ncell + 255) / 256;
+        hipLaunchKernelGGL((k_finish_pull<DIM, CL, ST>), dim3(nb), dim3(256), 0, st, a, jz, jx);
+        if constexpr (DIM == 2) {
+            hipLaunchKernelGGL(k_finish_b2d, dim3(nb), dim3(256), 0, st, a);
+            hipLaunchKernelGGL(k_finish_e2d, dim3(nb), dim3(256), 0, st, a, (const double *)jz,
+                               (const double *)jx);
+        }
+    }
+    static void init_pops(void *dst, const double *A, const double *uz, const double *ux,
+                          const double *aref, int ncell, double lam, hipStream_t st)
+    {
+        const int nb = (ncell + 255) / 256;
+        hipLaunchKernelGGL((k_init_pops<DIM, CL, ST>), dim3(nb), dim3(256), 0, st, dst, A, uz, ux,
+                           aref, ncell, lam);
+    }
+    static void read_moment(const StepArgs &a, int which, double *out, hipStream_t st)
+    {
+        const int nb = (a.ncell + 255) / 256;
+        hipLaunchKernelGGL((k_read_moment<DIM, CL, ST>), dim3(nb), dim3(256), 0, st, a, which, out);
+    }
+    static void diag(const StepArgs &a, double *part, int nblk, double *out, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_diag_partial<DIM, CL, ST>), dim3(nblk), dim3(256), 0, st, a, part);
+        hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, st, (const double *)part, nblk, out);
+    }
+};
+
+struct Ops {
+    void (*step)(const StepArgs &, hipStream_t);
+    void (*finish)(const StepArgs &, double *, double *, hipStream_t);
+    void (*init_pops)(void *, const double *, const double *, const double *, const double *, int,
+                      double, hipStream_t);
+    void (*read_moment)(const StepArgs &, int, double *, hipStream_t);
+    void (*diag)(const StepArgs &, double *, int, double *, hipStream_t);
+};
+
+template <int DIM, int CL, class ST> Ops ops_of()
+{
+    using I = Impl<DIM, CL, ST>;
+    return Ops{&I::step, &I::finish, &I::init_pops, &I::read_moment, &I::diag};
+}
+
+template <int DIM, int CL> Ops ops_st(int storage)
+{
+    if (storage == LBW_FP64) return ops_of<DIM, CL, double>();
+    if (storage == LBW_FP32) return ops_of<DIM, CL, float>();
+    return ops_of<DIM, CL, __half>();
+}
+
+Ops ops_for(const lbw_grid_desc &g)
+{
+    if (g.dims == 1) return g.closure == LBW_LEC ? ops_st<1, LEC>(g.storage) : ops_st<1, WARMC>(g.storage);
+    return g.closure == LBW_LEC ? ops_st<2, LEC>(g.storage) : ops_st<2, WARMC>(g.storage);
+}
+
+double lambda_rest(double mu, double D) { return 0.5 * (D * mu + std::sqrt(D * D * mu * mu + 4.0)); }
+
+// Storage reference A_ref per scalar: zero for FP64 / FP32 storage; the rest
+// state for FP16 deviations (n = 1, lambda_0, lambda_0 mu on the populated
+// pressure diagonal, zero momenta).
+void fill_aref(lbw_sim *s)
+{
+    const lbw_grid_desc &g = s->g;
+    for (int k = 0; k < 8; ++k) s->aref_host[k] = 0.0;
+    if (g.storage != LBW_FP16DEV) return;
+    s->aref_host[0] = 1.0;
+    if (g.closure == LBW_WARMC) {
+        const double l0 = lambda_rest(s->mu, g.dvel);
+        s->aref_host[1] = l0;
+        if (g.dims == 1) {
+            s->aref_host[3] = l0 * s->mu;
+        } else {
+            s->aref_host[4] = l0 * s->mu;
+            if (g.dvel >= 3.0) { s->aref_host[5] = l0 * s->mu; s->aref_host[6] = l0 * s->mu; }
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t lbw_workspace_bytes(const lbw_grid_desc *grid)
+{
+    if (!grid_valid(grid, nullptr)) return 0;
+    return make_layout(grid).total;
+}
+
+const char *lbw_version(void) { return "lbwake 0.1 (gfx950)"; }
+
+lbw_status lbw_create(const lbw_grid_desc *grid, void *ws, size_t ws_bytes, void *stream,
+                      lbw_sim **out)
+{
+    if (!out) return LBW_ERR_ARG;
+    *out = nullptr;
+    std::string why;
+    if (!grid_valid(grid, &why)) return LBW_ERR_ARG;
+    if (!(grid->tau_tilde > 0.5)) return LBW_ERR_UNSTABLE;
+    if (grid->dt > grid->delta / std::sqrt((double)grid->dims) * (1.0 + 1e-12)) return LBW_ERR_UNSTABLE;
+    const Layout L = make_layout(grid);
+    if (!ws || ws_bytes < L.total || ((uintptr_t)ws % ALIGN) != 0) return LBW_ERR_WORKSPACE;
+    lbw_sim *s = new lbw_sim();
+    s->g = *grid;
+    s->L = L;
+    s->ws = (char *)ws;
+    s->stream = (hipStream_t)stream;
+    s->pcur = s->fcur = 0;
+    s->initialized = s->canonical = s->lag_valid = false;
+    s->step = 0;
+    s->mu = 0.0;
+    s->drv = Driver{};
+    s->timing = false;
+    s->ev_used = 0;
+    s->kernel_ms = 0.0;
+    s->launches = 0;
+    *out = s;
+    return LBW_OK;
+}
+
+void lbw_destroy(lbw_sim *s)
+{
+    if (!s) return;
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    delete s;
+}
+
+static lbw_status drain_timing(lbw_sim *s)
+{
+    if (s->ev_used == 0) return LBW_OK;
+    HIPCHK(s, hipEventSynchronize(s->ev[s->ev_used - 1]));
+    for (int i = 0; i + 1 < s->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIPCHK(s, hipEventElapsedTime(&ms, s->ev[i], s->ev[i + 1]));
+        s->kernel_ms += ms;
+        s->launches += 1;
+    }
+    s->ev_used = 0;
+    return LBW_OK;
+}
+
+lbw_status lbw_set_timing(lbw_sim *s, int enable)
+{
+    if (!s) return LBW_ERR_ARG;
+    lbw_status st = drain_timing(s);
+    if (st != LBW_OK) return st;
+    if (enable && s->ev.empty()) {
+        s->ev.resize(2048);
+        for (auto &e : s->ev) HIPCHK(s, hipEventCreate(&e));
+    }
+    s->timing = enable != 0;
+    s->kernel_ms = 0.0;
+    s->launches = 0;
+    return LBW_OK;
+}
+
+lbw_status lbw_get_timing(lbw_sim *s, double *kernel_ms, long *launches)
+{
+    if (!s || !kernel_ms || !launches) return LBW_ERR_ARG;
+    lbw_status st = drain_timing(s);
+    if (st != LBW_OK) return st;
+    *kernel_ms = s->kernel_ms;
+    *launches = s->launches;
+    return LBW_OK;
+}
+
+const char *lbw_last_error(const lbw_sim *s) { return s ? s->err.c_str() : "NULL simulation"; }
+
+long lbw_step_count(const lbw_sim *s) { return s ? s->step : -1; }
+
+static lbw_status reset_common(lbw_sim *s, double mu)
+{
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    s->mu = mu;
+    fill_aref(s);
+    HIPCHK(s, hipMemcpyAsync(s->ws + s->L.aref, s->aref_host, 8 * sizeof(double),
+                             hipMemcpyHostToDevice, s->stream));
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < 3; ++f)
+            HIPCHK(s, hipMemsetAsync(s->ws + s->L.fld[b][f], 0, nc * 8, s->stream));
+    if (s->L.lag != s->L.stage)
+        HIPCHK(s, hipMemsetAsync(s->ws + s->L.lag, 0, s->L.stage - s->L.lag, s->stream));
+    HIPCHK(s, hipMemsetAsync(s->ws + s->L.fallbacks, 0, 8, s->stream));
+    s->pcur = s->fcur = 0;
+    s->canonical = true;
+    s->lag_valid = false;
+    s->step = 0;
+    s->drv = Driver{};
+    s->initialized = true;
+    return LBW_OK;
+}
+
+static lbw_status upload_and_init(lbw_sim *s, const std::vector<double> &A, const std::vector<double> &uz,
+                                  const std::vector<double> &ux)
+{
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    const int K = s->L.K;
+    double *stage = (double *)(s->ws + s->L.stage);
+    // stage holds A [K][nc]; the velocities go to the other population buffer
+    // (free until the first step) as scratch
+    double *uzd = (double *)(s->ws + s->L.pop[1]);
+    double *uxd = uzd + nc;
+    if (s->L.pop[1] - s->L.pop[0] < 2 * nc * 8) {
+        // populations smaller than two FP64 planes (FP16 1D): use the field buffers
+        uzd = (double *)(s->ws + s->L.fld[1][0]);
+        uxd = (double *)(s->ws + s->L.fld[1][1]);
+    }
+    HIPCHK(s, hipMemcpyAsync(stage, A.data(), (size_t)K * nc * 8, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(uzd, uz.data(), nc * 8, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(uxd, ux.data(), nc * 8, hipMemcpyHostToDevice, s->stream));
+    ops_for(s->g).init_pops(s->ws + s->L.pop[0], stage, uzd, uxd, (const double *)(s->ws + s->L.aref),
+                            (int)nc, s->g.delta / s->g.dt, s->stream);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int f = 0; f < 3; ++f)
+        HIPCHK(s, hipMemsetAsync(s->ws + s->L.fld[1][f], 0, nc * 8, s->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_init_plasma(lbw_sim *s, const lbw_plasma_desc *p)
+{
+    if (!s || !p) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!(p->mu >= 0.0)) return fail(s, LBW_ERR_ARG, "mu must be >= 0");
+    lbw_status st = reset_common(s, p->mu);
+    if (st != LBW_OK) return st;
+    const lbw_grid_desc &g = s->g;
+    const size_t nc = (size_t)g.nz * g.nx;
+    const int K = s->L.K;
+    const double D = g.dvel, mu = p->mu;
+    std::vector<double> A((size_t)K * nc, 0.0), uz(nc, 0.0), ux(nc, 0.0);
+    for (size_t c = 0; c < nc; ++c) {
+        const double n = p->n_init ? p->n_init[c] : 1.0;
+        const double vz = p->uz_init ? p->uz_init[c] : 0.0;
+        const double vx = (p->ux_init && g.dims == 2) ? p->ux_init[c] : 0.0;
+        const double uu = vz * vz + vx * vx;
+        if (!(n > 0.0) || !(uu < 1.0) || !std::isfinite(n) || !std::isfinite(uu))
+            return fail(s, LBW_ERR_NONFINITE, "initial density must be positive and |u| < 1");
+        const double gam = 1.0 / std::sqrt(1.0 - uu);
+        uz[c] = vz;
+        ux[c] = vx;
+        A[c] = n;
+        if (g.closure == LBW_LEC) {
+            // A_1 = [1 + (1 + D/2) mu (n/gamma)^{2/D}] n gamma u (eq. lb-ade-lec-comps-A)
+            const double h = 1.0 + (1.0 + 0.5 * D) * mu * std::pow(n / gam, 2.0 / D);
+            A[1 * nc + c] = h * n * gam * vz;
+            if (g.dims == 2) A[2 * nc + c] = h * n * gam * vx;
+        } else {
+            // rest state diag(0, P, P, P) on the D populated directions, boosted
+            // to the lab (eq. double-boost); lambda = gamma lambda_0 (eq. traces3)
+            const double P = n / gam * mu, lam = gam * lambda_rest(mu, D);
+            const double v[3] = {vx, 0.0, vz}, p0[3] = {D >= 3.0 ? P : 0.0, D >= 3.0 ? P : 0.0, P};
+            double th[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double acc = 0.0;
+                    for (int m = 0; m < 3; ++m) {
+                        const double Lim = (i == m ? 1.0 : 0.0) + (uu > 0.0 ? (gam - 1.0) * v[i] * v[m] / uu : 0.0);
+                        const double Ljm = (j == m ? 1.0 : 0.0) + (uu > 0.0 ? (gam - 1.0) * v[j] * v[m] / uu : 0.0);
+                        acc += Lim * Ljm * p0[m];
+                    }
+                    th[i][j] = acc;
+                }
+            A[1 * nc + c] = n * lam;
+            A[2 * nc + c] = n * lam * vz;
+            if (g.dims == 1) {
+                A[3 * nc + c] = lam * th[2][2];
+            } else {
+                A[3 * nc + c] = n * lam * vx;
+                A[4 * nc + c] = lam * th[2][2];
+                A[5 * nc + c] = lam * th[0][0];
+                A[6 * nc + c] = lam * th[1][1];
+                A[7 * nc + c] = lam * th[0][2];
+            }
+        }
+    }
+    return upload_and_init(s, A, uz, ux);
+}
+
+lbw_status lbw_init_moments(lbw_sim *s, double mu, const double *Ah, const double *uzh, const double *uxh)
+{
+    if (!s || !Ah) return fail(s, LBW_ERR_ARG, "NULL argument");
+    lbw_status st = reset_common(s, mu);
+    if (st != LBW_OK) return st;
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    std::vector<double> A(Ah, Ah + (size_t)s->L.K * nc), uz(nc, 0.0), ux(nc, 0.0);
+    if (uzh) uz.assign(uzh, uzh + nc);
+    if (uxh && s->g.dims == 2) ux.assign(uxh, uxh + nc);
+    return upload_and_init(s, A, uz, ux);
+}
+
+lbw_status lbw_init_driver(lbw_sim *s, const lbw_driver_desc *d, int init_fields)
+{
+    if (!s || !d) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (d->alpha != 0.0 && (!(d->sigma_z > 0) || (s->g.dims == 2 && !(d->sigma_x > 0))))
+        return fail(s, LBW_ERR_ARG, "bunch widths must be positive");
+    if (d->nslices < 0 || d->nslices > MAX_SLICES || (d->nslices > 0 && !d->slice_w) ||
+        (d->nslices > 0 && !(d->slice_zmax > d->slice_zmin)))
+        return fail(s, LBW_ERR_ARG, "invalid slice description");
+    Driver v{};
+    v.alpha = d->alpha;
+    v.sigma_z = d->sigma_z;
+    v.sigma_x = d->sigma_x;
+    v.z0 = d->z0;
+    v.x0 = d->x0;
+    v.nslices = d->nslices;
+    v.slice_zmin = d->slice_zmin;
+    v.slice_zmax = d->slice_zmax;
+    v.slice_w = (const double *)(s->ws + s->L.slice);
+    if (d->nslices > 0)
+        HIPCHK(s, hipMemcpyAsync(s->ws + s->L.slice, d->slice_w, d->nslices * sizeof(double),
+                                 hipMemcpyHostToDevice, s->stream));
+    s->drv = v;
+    if (init_fields && d->alpha != 0.0) {
+        if (!s->canonical) return fail(s, LBW_ERR_STATE, "fields can only be set on a canonical state");
+        StepArgs a = base_args(s);
+        const int nb = (a.ncell + 255) / 256;
+        double *ez = (double *)(s->ws + s->L.fld[s->fcur][0]);
+        double *ex = (double *)(s->ws + s->L.fld[s->fcur][1]);
+        double *by = (double *)(s->ws + s->L.fld[s->fcur][2]);
+        if (s->g.dims == 1)
+            hipLaunchKernelGGL(k_init_fields<1>, dim3(nb), dim3(256), 0, s->stream, a, ez, ex, by);
+        else
+            hipLaunchKernelGGL(k_init_fields<2>, dim3(nb), dim3(256), 0, s->stream, a, ez, ex, by);
+        HIPCHK(s, hipGetLastError());
+    }
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_set_field(lbw_sim *s, int which, const double *host, size_t count)
+{
+    if (!s || !host) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    if (count != nc) return fail(s, LBW_ERR_ARG, "count must be nx*nz");
+    if (which < 0 || which > 2 || (s->g.dims == 1 && which != LBW_EZ))
+        return fail(s, LBW_ERR_ARG, "which must be a Yee array of this grid");
+    HIPCHK(s, hipMemcpyAsync(s->ws + s->L.fld[s->fcur][which], host, nc * 8, hipMemcpyHostToDevice,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_step(lbw_sim *s, int nsteps)
+{
+    if (!s) return LBW_ERR_ARG;
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (nsteps < 0) return fail(s, LBW_ERR_ARG, "nsteps must be >= 0");
+    if (nsteps == 0) return LBW_OK;
+    const Ops ops = ops_for(s->g);
+    for (int t = 0; t < nsteps; ++t) {
+        StepArgs a = base_args(s);
+        set_io(s, a);
+        a.do_pull = s->canonical ? 0 : 1;
+        a.do_maxwell = s->canonical ? 0 : 1;
+        a.lag_init = s->lag_valid ? 0 : 1;
+        if (s->timing) {
+            if (s->ev_used + 2 > (int)s->ev.size()) {
+                lbw_status st = drain_timing(s);
+                if (st != LBW_OK) return st;
+            }
+            HIPCHK(s, hipEventRecord(s->ev[s->ev_used++], s->stream));
+            ops.step(a, s->stream);
+            HIPCHK(s, hipEventRecord(s->ev[s->ev_used++], s->stream));
+        } else {
+            ops.step(a, s->stream);
+        }
+        s->pcur ^= 1;
+        s->fcur ^= 1;
+        s->canonical = false;
+        s->lag_valid = true;
+        s->step++;
+    }
+    HIPCHK(s, hipGetLastError());
+    // bring the state to canonical form (f^n, E^n, B^{n-1/2})
+    StepArgs a = base_args(s);
+    set_io(s, a);
+    double *stage = (double *)(s->ws + s->L.stage);
+    ops.finish(a, stage, stage + (size_t)a.ncell, s->stream);
+    HIPCHK(s, hipGetLastError());
+    s->pcur ^= 1;
+    s->fcur ^= 1;
+    s->canonical = true;
+    return LBW_OK;
+}
+
+static lbw_status read_common(lbw_sim *s, int which, double *dev_out)
+{
+    StepArgs a = base_args(s);
+    set_io(s, a);
+    ops_for(s->g).read_moment(a, which, dev_out, s->stream);
+    HIPCHK(s, hipGetLastError());
+    return LBW_OK;
+}
+
+lbw_status lbw_read_moment(lbw_sim *s, int which, double *host_out, size_t count)
+{
+    if (!s || !host_out) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    if (count != nc) return fail(s, LBW_ERR_ARG, "count must be nx*nz");
+    if (which < 0 || which >= LBW_NMOMENTS) return fail(s, LBW_ERR_ARG, "unknown moment");
+    double *stage = (double *)(s->ws + s->L.stage);
+    lbw_status st = read_common(s, which, stage);
+    if (st != LBW_OK) return st;
+    HIPCHK(s, hipMemcpyAsync(host_out, stage, nc * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_read_moment_device(lbw_sim *s, int which, double *dev_out)
+{
+    if (!s || !dev_out) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (which < 0 || which >= LBW_NMOMENTS) return fail(s, LBW_ERR_ARG, "unknown moment");
+    return read_common(s, which, dev_out);
+}
+
+lbw_status lbw_read_field(lbw_sim *s, int which, int at_nodes, double *host_out, size_t count)
+{
+    if (!s || !host_out) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    if (count != nc) return fail(s, LBW_ERR_ARG, "count must be nx*nz");
+    if (which < 0 || which >= LBW_NFIELDS || (which == LBW_WAKE_X && !at_nodes))
+        return fail(s, LBW_ERR_ARG, "unknown field");
+    StepArgs a = base_args(s);
+    set_io(s, a);
+    double *stage = (double *)(s->ws + s->L.stage);
+    const int nb = (a.ncell + 255) / 256;
+    if (s->g.dims == 1)
+        hipLaunchKernelGGL(k_read_field<1>, dim3(nb), dim3(256), 0, s->stream, a, which, at_nodes, stage);
+    else
+        hipLaunchKernelGGL(k_read_field<2>, dim3(nb), dim3(256), 0, s->stream, a, which, at_nodes, stage);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(host_out, stage, nc * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_diagnostics(lbw_sim *s, double *out)
+{
+    if (!s || !out) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    StepArgs a = base_args(s);
+    set_io(s, a);
+    double *part = (double *)(s->ws + s->L.part);
+    double *dout = (double *)(s->ws + s->L.diag);
+    ops_for(s->g).diag(a, part, s->L.nblk_diag, dout, s->stream);
+    HIPCHK(s, hipGetLastError());
+    double d[NDIAG];
+    unsigned int fb = 0;
+    HIPCHK(s, hipMemcpyAsync(d, dout, sizeof(d), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(&fb, s->ws + s->L.fallbacks, sizeof(fb), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const double nc = (double)s->g.nz * s->g.nx;
+    out[0] = d[0];
+    out[1] = d[1];
+    out[2] = d[2];
+    out[3] = std::sqrt(d[3] / nc);
+    out[4] = d[5];
+    out[5] = d[4];
+    out[6] = (double)fb;
+    out[7] = (double)s->step;
+    if (d[4] > 0 || !std::isfinite(d[0])) return fail(s, LBW_ERR_NONFINITE, "non-finite values in the state");
+    return LBW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Checkpoint format: a fixed header followed by the canonical populations,
+// the three Yee arrays and the lagged values.
+namespace {
+struct StateHeader {
+    char magic[8];
+    int dims, nz, nx, closure, storage, lag_valid;
+    long step;
+    double mu;
+    unsigned int fallbacks, pad;
+};
+}  // namespace
+
+size_t lbw_state_bytes(const lbw_sim *s)
+{
+    if (!s) return 0;
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    return sizeof(StateHeader) + nc * s->L.K * s->L.Q * storage_size(s->g.storage) + 3 * nc * 8 +
+           (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
+}
+
+lbw_status lbw_save_state(lbw_sim *s, void *host, size_t bytes)
+{
+    if (!s || !host) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (bytes < lbw_state_bytes(s)) return fail(s, LBW_ERR_ARG, "buffer too small");
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    StateHeader h{};
+    std::memcpy(h.magic, "LBWSTAT1", 8);
+    h.dims = s->g.dims; h.nz = s->g.nz; h.nx = s->g.nx; h.closure = s->g.closure;
+    h.storage = s->g.storage; h.lag_valid = s->lag_valid; h.step = s->step; h.mu = s->mu;
+    HIPCHK(s, hipMemcpyAsync(&h.fallbacks, s->ws + s->L.fallbacks, 4, hipMemcpyDeviceToHost, s->stream));
+    char *p = (char *)host + sizeof(StateHeader);
+    const size_t popb = nc * s->L.K * s->L.Q * storage_size(s->g.storage);
+    HIPCHK(s, hipMemcpyAsync(p, s->ws + s->L.pop[s->pcur], popb, hipMemcpyDeviceToHost, s->stream));
+    p += popb;
+    for (int f = 0; f < 3; ++f, p += nc * 8)
+        HIPCHK(s, hipMemcpyAsync(p, s->ws + s->L.fld[s->fcur][f], nc * 8, hipMemcpyDeviceToHost, s->stream));
+    const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
+    if (lagb) HIPCHK(s, hipMemcpyAsync(p, s->ws + s->L.lag, lagb, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    std::memcpy(host, &h, sizeof(h));
+    return LBW_OK;
+}
+
+lbw_status lbw_load_state(lbw_sim *s, const void *host, size_t bytes)
+{
+    if (!s || !host) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (bytes < lbw_state_bytes(s)) return fail(s, LBW_ERR_ARG, "buffer too small");
+    StateHeader h;
+    std::memcpy(&h, host, sizeof(h));
+    if (std::memcmp(h.magic, "LBWSTAT1", 8) != 0 || h.dims != s->g.dims || h.nz != s->g.nz ||
+        h.nx != s->g.nx || h.closure != s->g.closure || h.storage != s->g.storage)
+        return fail(s, LBW_ERR_ARG, "state does not match this grid");
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    s->mu = h.mu;
+    fill_aref(s);
+    HIPCHK(s, hipMemcpyAsync(s->ws + s->L.aref, s->aref_host, 8 * sizeof(double), hipMemcpyHostToDevice,
+                             s->stream));
+    s->pcur = s->fcur = 0;
+    const char *p = (const char *)host + sizeof(StateHeader);
+    const size_t popb = nc * s->L.K * s->L.Q * storage_size(s->g.storage);
+    HIPCHK(s, hipMemcpyAsync(s->ws + s->L.pop[0], p, popb, hipMemcpyHostToDevice, s->stream));
+    p += popb;
+    for (int f = 0; f < 3; ++f, p += nc * 8)
+        HIPCHK(s, hipMemcpyAsync(s->ws + s->L.fld[0][f], p, nc * 8, hipMemcpyHostToDevice, s->stream));
+    const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
+    if (lagb) HIPCHK(s, hipMemcpyAsync(s->ws + s->L.lag, p, lagb, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->ws + s->L.fallbacks, &h.fallbacks, 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->step = h.step;
+    s->lag_valid = h.lag_valid != 0;
+    s->canonical = true;
+    s->initialized = true;
+    return LBW_OK;
+}
+
+}  // extern "C"

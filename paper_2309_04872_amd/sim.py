@@ -1,0 +1,167 @@
+"""Python binding of the C ABI: one ``Sim`` per simulation. PyTorch provides
+the device workspace and the stream; the binding only marshals arguments."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+
+class LbwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Sim:
+    """A 1D or 2D simulation bound to a torch-allocated workspace on ``device``.
+
+    Parameters mirror ``lbw_grid_desc``: ``closure`` in {'lec', 'warmc'},
+    ``storage`` in {'fp64', 'fp32', 'fp16dev'}, ``bc_z``/``bc_x`` in
+    {'open', 'periodic'}. ``dt`` defaults to delta / 10 and ``tau_tilde`` to
+    0.52 (1D) / 0.53 (2D), the paper's choices (Sec. 5).
+    """
+
+    def __init__(self, dims, nz, nx=1, delta=2 * np.pi / 128, dt=None, tau_tilde=None,
+                 closure="lec", dvel=None, storage="fp64", bc_z="open", bc_x="open",
+                 device="cuda:0", stream=None):
+        import torch
+
+        self._lib = _lib.load()
+        if dt is None:
+            dt = 0.1 * delta
+        if tau_tilde is None:
+            tau_tilde = 0.52 if dims == 1 else 0.53
+        if dvel is None:
+            dvel = 1.0 if dims == 1 else 3.0
+        self.dims, self.nz, self.nx = dims, nz, nx
+        self.shape = (nx, nz)
+        self.ncell = nx * nz
+        self.closure = closure
+        self.grid = _lib.GridDesc(dims, nz, nx, delta, dt, tau_tilde, _lib.CLOSURES[closure],
+                                  float(dvel), _lib.STORAGE[storage], _lib.BCS[bc_z], _lib.BCS[bc_x])
+        nbytes = self._lib.lbw_workspace_bytes(ctypes.byref(self.grid))
+        if nbytes == 0:
+            raise LbwError(-1, "invalid grid descriptor")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self._lib.lbw_create(ctypes.byref(self.grid), ctypes.c_void_p(self.workspace.data_ptr()),
+                                  nbytes, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise LbwError(rc, "lbw_create rejected the grid")
+        self._h = h
+
+    # ------------------------------------------------------------------
+    def _check(self, rc):
+        if rc != 0:
+            raise LbwError(rc, self._lib.lbw_last_error(self._h).decode())
+
+    def _arr(self, a):
+        if a is None:
+            return None
+        return np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), self.shape))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lbw_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def init_plasma(self, mu, n=None, uz=None, ux=None):
+        n, uz, ux = self._arr(n), self._arr(uz), self._arr(ux)
+        p = _lib.PlasmaDesc(mu, _dp(n), _dp(uz), _dp(ux))
+        self._check(self._lib.lbw_init_plasma(self._h, ctypes.byref(p)))
+        return self
+
+    def init_moments(self, mu, A, uz=None, ux=None):
+        K = {("lec", 1): 2, ("lec", 2): 3, ("warmc", 1): 4, ("warmc", 2): 8}[(self.closure, self.dims)]
+        A = np.ascontiguousarray(np.asarray(A, dtype=np.float64).reshape(K, *self.shape))
+        uz, ux = self._arr(uz), self._arr(ux)
+        self._check(self._lib.lbw_init_moments(self._h, mu, _dp(A), _dp(uz), _dp(ux)))
+        return self
+
+    def init_driver(self, alpha, sigma_z, sigma_x=1.0, z0=None, x0=0.0, slice_w=None,
+                    slice_zmin=0.0, slice_zmax=0.0, init_fields=True):
+        if z0 is None:
+            z0 = 6.0 * sigma_z
+        w = None if slice_w is None else np.ascontiguousarray(slice_w, dtype=np.float64)
+        d = _lib.DriverDesc(alpha, sigma_z, sigma_x, z0, x0, 0 if w is None else len(w), _dp(w),
+                            slice_zmin, slice_zmax)
+        self._check(self._lib.lbw_init_driver(self._h, ctypes.byref(d), int(bool(init_fields))))
+        return self
+
+    def set_field(self, which, values):
+        v = self._arr(values)
+        self._check(self._lib.lbw_set_field(self._h, _lib.FIELDS[which], _dp(v), v.size))
+        return self
+
+    def step(self, nsteps=1):
+        self._check(self._lib.lbw_step(self._h, int(nsteps)))
+        return self
+
+    @property
+    def step_count(self):
+        return int(self._lib.lbw_step_count(self._h))
+
+    def read(self, which):
+        out = np.empty(self.shape, dtype=np.float64)
+        self._check(self._lib.lbw_read_moment(self._h, _lib.MOMENTS[which], _dp(out), out.size))
+        return out if self.dims == 2 else out[0]
+
+    def read_device(self, which):
+        import torch
+
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._check(self._lib.lbw_read_moment_device(self._h, _lib.MOMENTS[which],
+                                                     ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def field(self, which, at_nodes=True):
+        out = np.empty(self.shape, dtype=np.float64)
+        self._check(self._lib.lbw_read_field(self._h, _lib.FIELDS[which], int(bool(at_nodes)),
+                                             _dp(out), out.size))
+        return out if self.dims == 2 else out[0]
+
+    def diagnostics(self, check=True):
+        out = np.zeros(8)
+        rc = self._lib.lbw_diagnostics(self._h, _dp(out))
+        if check:
+            self._check(rc)
+        return out
+
+    def set_timing(self, enable=True):
+        self._check(self._lib.lbw_set_timing(self._h, int(bool(enable))))
+        return self
+
+    def get_timing(self):
+        """(summed fused-kernel milliseconds, launches) since set_timing(True)."""
+        ms, n = ctypes.c_double(), ctypes.c_long()
+        self._check(self._lib.lbw_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def save_state(self) -> bytes:
+        n = self._lib.lbw_state_bytes(self._h)
+        buf = ctypes.create_string_buffer(n)
+        self._check(self._lib.lbw_save_state(self._h, ctypes.cast(buf, ctypes.c_void_p), n))
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = ctypes.create_string_buffer(data, len(data))
+        self._check(self._lib.lbw_load_state(self._h, ctypes.cast(buf, ctypes.c_void_p), len(data)))
+        return self

@@ -1,0 +1,78 @@
+"""Seeded synthetic inputs and the named workloads (configuration data only,
+none of the method's arithmetic). Shared by the tests, the benchmark and the
+oracle-side checks; it imports neither the HIP binding nor the oracle.
+
+The paper simulates no dataset: every input is a uniform plasma (optionally
+with seeded density noise) and an analytic driver bunch (Sec. 5). Grid
+spacings are fractions of the plasma wavelength lambda_p = 2 pi / k_p; the
+time step is delta / 10 and tau~ is 0.52 (1D) / 0.53 (2D), the paper's ratios.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+LAMBDA_P = 2.0 * math.pi
+
+
+def density_noise(shape, amp, seed):
+    """n = 1 + amp * U(-1, 1), numpy PCG64 stream of ``seed``."""
+    rng = np.random.default_rng(seed)
+    return 1.0 + amp * rng.uniform(-1.0, 1.0, size=shape)
+
+
+def slice_weights(nslices, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=nslices)
+
+
+def batch_scan(n_inst=256, seed=0):
+    """Parameter scan of independent 1D instances: Nz ~ U{1024..16384},
+    n_b/n0 log-uniform [0.01, 3], sigma_z ~ U[0.3, 2], T log-uniform
+    [1e-4, 1e-1] m c^2, closures alternating."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_inst):
+        out.append(dict(
+            nz=int(rng.integers(1024, 16385)),
+            alpha=float(10 ** rng.uniform(math.log10(0.01), math.log10(3.0))),
+            sigma_z=float(rng.uniform(0.3, 2.0)),
+            mu=float(10 ** rng.uniform(-4.0, -1.0)),
+            closure="lec" if i % 2 == 0 else "warmc",
+        ))
+    return out
+
+
+# Named workloads: grid, closure, storage, plasma, driver, length.
+WORKLOADS = {
+    "wake1d_lec_fp64": dict(
+        dims=1, nz=4096, nx=1, delta=LAMBDA_P / 128, closure="lec", dvel=1.0, storage="fp64",
+        mu=1e-3, noise=1e-8, seed=0, alpha=0.1, sigma_z=0.5, sigma_x=1.0, steps=4096),
+    "wake2d_lec_fp32": dict(
+        dims=2, nz=2048, nx=512, delta=LAMBDA_P / 64, closure="lec", dvel=3.0, storage="fp32",
+        mu=1e-2, noise=0.0, seed=0, alpha=1.0, sigma_z=1.0, sigma_x=0.5, steps=8000),
+    "wake2d_warmc": dict(
+        dims=2, nz=4096, nx=1024, delta=LAMBDA_P / 64, closure="warmc", dvel=3.0, storage="fp64",
+        mu=5e-2, noise=0.0, seed=0, alpha=2.0, sigma_z=1.0, sigma_x=0.5, steps=8000),
+    "wake2d_lec_adjoint": dict(
+        dims=2, nz=1024, nx=256, delta=LAMBDA_P / 64, closure="lec", dvel=3.0, storage="fp32",
+        mu=1e-2, noise=0.0, seed=0, alpha=0.5, sigma_z=1.0, sigma_x=0.5, steps=2000,
+        nslices=64, slice_lo=0.5, slice_hi=1.5),
+}
+
+
+def workload(name, **overrides):
+    w = dict(WORKLOADS[name])
+    w.update(overrides)
+    w["dt"] = 0.1 * w["delta"]
+    w["tau_tilde"] = 0.52 if w["dims"] == 1 else 0.53
+    w["z0"] = 6.0 * w["sigma_z"]
+    return w
+
+
+def initial_density(w):
+    shape = (w["nx"], w["nz"])
+    if w.get("noise", 0.0) > 0.0:
+        return density_noise(shape, w["noise"], w["seed"])
+    return np.ones(shape)

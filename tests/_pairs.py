@@ -1,0 +1,67 @@
+"""Build the same seeded problem on the HIP library and on the CPU oracle."""
+import numpy as np
+
+import oracle
+from paper_2309_04872_amd.sim import Sim
+
+CL = {"lec": oracle.LEC, "warmc": oracle.WARMC}
+BC = {"open": oracle.OPEN, "periodic": oracle.PERIODIC}
+
+FLUID = ["n", "uz", "ux", "gamma", "n0", "p0", "mz", "mx"]
+WARM = ["lambda", "thzz", "thxx", "thyy", "thxz", "ppar"]
+FIELDS = ["ez", "ex", "by"]
+
+
+def make_pair(dims, nz, nx=1, delta=2 * np.pi / 128, closure="lec", dvel=None, storage="fp64",
+              bc_z="open", bc_x="open", mu=1e-2, n=None, uz=None, ux=None, driver=None,
+              tau_tilde=None, dt=None, oracle_only=False):
+    kw = dict(delta=delta, dt=dt, tau_tilde=tau_tilde)
+    o = oracle.Oracle(dims, nz, nx, closure=CL[closure], dvel=dvel, bc_z=BC[bc_z], bc_x=BC[bc_x],
+                      mu=mu, **{k: v for k, v in kw.items() if v is not None},
+                      **(_oracle_driver(driver) if driver else {}))
+    o.init(n=n, uz=uz, ux=ux, fields_from_driver=bool(driver))
+    if oracle_only:
+        return None, o
+    s = Sim(dims, nz, nx, closure=closure, dvel=dvel, storage=storage, bc_z=bc_z, bc_x=bc_x,
+            **{k: v for k, v in kw.items() if v is not None})
+    s.init_plasma(mu, n=n, uz=uz, ux=ux)
+    if driver:
+        s.init_driver(**driver, init_fields=True)
+    return s, o
+
+
+def _oracle_driver(d):
+    out = dict(alpha=d["alpha"], sigma_z=d["sigma_z"], sigma_x=d.get("sigma_x", 1.0),
+               z0=d.get("z0", 6.0 * d["sigma_z"]), x0=d.get("x0", 0.0))
+    if d.get("slice_w") is not None:
+        out.update(slice_w=d["slice_w"], slice_zmin=d["slice_zmin"], slice_zmax=d["slice_zmax"])
+    return out
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return np.linalg.norm(a)
+    return np.linalg.norm(a - b) / nb
+
+
+def compare(s, o, quantities, tol, report=None, slice_=None):
+    """Per-field relative L2 of the GPU result against the oracle."""
+    worst = {}
+    for q in quantities:
+        if q in FIELDS:
+            g, r = s.field(q, at_nodes=True), o.get(q)
+        elif q.endswith("_yee"):
+            g, r = s.field(q[:-4], at_nodes=False), o.get(q)
+        else:
+            g, r = s.read(q), o.get(q)
+        if slice_ is not None:
+            g, r = g[slice_], r[slice_]
+        assert np.all(np.isfinite(g)), q
+        e = rel_l2(g, r)
+        worst[q] = e
+    if report is not None:
+        report.update(worst)
+    bad = {q: e for q, e in worst.items() if not e <= tol}
+    assert not bad, f"relative L2 above {tol}: {bad}"
+    return worst

@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/lbwake.h declares, and rejects invalid grids before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2309_04872_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbwake.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbw_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.SO_PATH):
+        from paper_2309_04872_amd import build
+
+        build.build()
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert len(declared) >= 15
+    assert sorted(_lib.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.lbw_version()
+
+
+def _grid(**kw):
+    g = dict(dims=2, nz=64, nx=16, delta=0.1, dt=0.01, tau_tilde=0.53, closure=0, dvel=3.0,
+             storage=0, bc_z=0, bc_x=0)
+    g.update(kw)
+    return _lib.GridDesc(**g)
+
+
+def test_workspace_bytes(lib):
+    g = _grid()
+    n = lib.lbw_workspace_bytes(ctypes.byref(g))
+    nc = 64 * 16
+    # two FP64 population buffers of 3 x 9 planes plus six field planes at least
+    assert n >= 2 * 27 * nc * 8 + 6 * nc * 8
+    g32 = _grid(storage=1)
+    assert lib.lbw_workspace_bytes(ctypes.byref(g32)) < n
+    assert lib.lbw_workspace_bytes(ctypes.byref(_grid(dims=3))) == 0
+    assert lib.lbw_workspace_bytes(ctypes.byref(_grid(nz=2))) == 0
+    assert lib.lbw_workspace_bytes(ctypes.byref(_grid(dims=1, nx=4))) == 0
+    assert lib.lbw_workspace_bytes(ctypes.byref(_grid(closure=5))) == 0
+
+
+def _create(lib, g, ws=256 * 1024, nbytes=None):
+    h = ctypes.c_void_p()
+    if nbytes is None:
+        nbytes = lib.lbw_workspace_bytes(ctypes.byref(g))
+    rc = lib.lbw_create(ctypes.byref(g), ctypes.c_void_p(ws), nbytes, None, ctypes.byref(h))
+    return rc, h
+
+
+def test_create_validation(lib):
+    # a fake, aligned workspace address: lbw_create only records it
+    rc, h = _create(lib, _grid())
+    assert rc == 0 and h.value
+    assert lib.lbw_step_count(h) == 0
+    assert lib.lbw_step(h, 1) == -6  # LBW_ERR_STATE: step before init
+    assert b"init" in lib.lbw_last_error(h)
+    lib.lbw_destroy(h)
+    assert _create(lib, _grid(tau_tilde=0.5))[0] == -4           # BGK stability
+    assert _create(lib, _grid(dt=0.1))[0] == -4                  # 2D Courant
+    assert _create(lib, _grid(dims=1, nx=1, dt=0.1))[0] == 0      # 1D Courant limit dt = delta
+    assert _create(lib, _grid(), ws=256 * 1024 + 8)[0] == -2      # misaligned workspace
+    assert _create(lib, _grid(), nbytes=1024)[0] == -2            # too small
+    assert _create(lib, _grid(nz=1))[0] == -1

@@ -1,0 +1,274 @@
+"""Parity of the HIP library with the CPU oracle on identical seeded inputs,
+through the C ABI. Tolerances: per-field relative L2 <= 1e-10 with FP64
+populations, <= 1e-4 with FP32 populations (FP64 recovery)."""
+import numpy as np
+import pytest
+
+from _pairs import FIELDS, FLUID, WARM, compare, make_pair
+from paper_2309_04872_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4}
+
+
+def _quantities(closure, dims):
+    q = list(FLUID) + (list(WARM) if closure == "warmc" else [])
+    q += ["ez"] if dims == 1 else list(FIELDS) + ["ez_yee", "ex_yee", "by_yee"]
+    if dims == 1:
+        q = [x for x in q if x not in ("ux", "mx", "thxx", "thyy", "thxz")]
+    return q
+
+
+# ---------------------------------------------------------------------------
+# Small grids spanning several tiles with ragged tails (1D tile 256, 2D 32 x 8)
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_parity_1d_driven(closure, storage):
+    nz = 600
+    z = np.arange(nz)
+    n = workloads.density_noise((1, nz), 1e-3, 11)[0] + 0.02 * np.sin(2 * np.pi * z / 97)
+    s, o = make_pair(1, nz, closure=closure, storage=storage, mu=0.02, n=n,
+                     driver=dict(alpha=0.3, sigma_z=0.5, z0=3.0))
+    s.step(400)
+    o.step(400)
+    assert s.step_count == 400
+    compare(s, o, _quantities(closure, 1), TOL[storage])
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_parity_2d_driven(closure, storage):
+    nz, nx = 100, 20
+    d = 2 * np.pi / 32
+    n = workloads.density_noise((nx, nz), 1e-3, 5)
+    s, o = make_pair(2, nz, nx, delta=d, closure=closure, storage=storage, mu=0.03, n=n,
+                     driver=dict(alpha=0.8, sigma_z=1.0, sigma_x=0.5, z0=4.0, x0=0.1))
+    s.step(60)
+    o.step(60)
+    compare(s, o, _quantities(closure, 2), TOL[storage])
+
+
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_parity_2d_periodic_waves(closure):
+    nz, nx = 72, 40
+    d = 2 * np.pi / 24
+    zz, xx = np.meshgrid(np.arange(nz) * d, np.arange(nx) * d)
+    uz = 0.05 * np.sin(2 * np.pi * zz / (nz * d)) * np.cos(2 * np.pi * xx / (nx * d))
+    ux = 0.04 * np.cos(2 * np.pi * zz / (nz * d))
+    n = 1 + 0.05 * np.cos(2 * np.pi * xx / (nx * d))
+    s, o = make_pair(2, nz, nx, delta=d, closure=closure, mu=0.05, n=n, uz=uz, ux=ux,
+                     bc_z="periodic", bc_x="periodic")
+    s.step(90)
+    o.step(90)
+    compare(s, o, _quantities(closure, 2), 1e-10)
+
+
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_parity_1d_periodic_relativistic(closure):
+    nz = 300
+    z = np.arange(nz)
+    uz = 0.6 * np.sin(2 * np.pi * z / nz)
+    s, o = make_pair(1, nz, closure=closure, mu=0.05, uz=uz, bc_z="periodic")
+    s.step(500)
+    o.step(500)
+    compare(s, o, _quantities(closure, 1), 1e-10)
+
+
+def test_parity_2d_slices():
+    nz, nx = 96, 24
+    d = 2 * np.pi / 32
+    w = workloads.slice_weights(16, 0.5, 1.5, 3)
+    drv = dict(alpha=0.5, sigma_z=1.0, sigma_x=0.5, z0=4.0, slice_w=w, slice_zmin=-3.0,
+               slice_zmax=3.0)
+    s, o = make_pair(2, nz, nx, delta=d, closure="lec", mu=0.01, driver=drv)
+    s.step(50)
+    o.step(50)
+    compare(s, o, _quantities("lec", 2), 1e-10)
+
+
+def test_minimum_sizes():
+    for dims, nz, nx in ((1, 4, 1), (2, 4, 4)):
+        for closure in ("lec", "warmc"):
+            n = workloads.density_noise((nx, nz), 1e-2, 1)
+            s, o = make_pair(dims, nz, nx, closure=closure, mu=0.05, n=n)
+            s.step(30)
+            o.step(30)
+            compare(s, o, _quantities(closure, dims), 1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads in the launch configuration the benchmark times.
+
+def test_full_size_wake1d_lec_fp64():
+    """The 1D local-equilibrium wake, 4096 cells, 4096 steps, FP64, noise 1e-8."""
+    w = workloads.workload("wake1d_lec_fp64")
+    n = workloads.initial_density(w)[0]
+    s, o = make_pair(1, w["nz"], delta=w["delta"], closure="lec", dvel=w["dvel"], mu=w["mu"], n=n,
+                     driver=dict(alpha=w["alpha"], sigma_z=w["sigma_z"], z0=w["z0"]))
+    s.step(w["steps"])
+    o.step(w["steps"])
+    compare(s, o, ["n", "uz", "ez", "gamma", "p0"], 1e-10)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_full_size_wake2d_lec(storage):
+    """2048 x 512 local-equilibrium wake, 10 steps against the oracle."""
+    w = workloads.workload("wake2d_lec_fp32")
+    s, o = make_pair(2, w["nz"], w["nx"], delta=w["delta"], closure="lec", dvel=w["dvel"],
+                     storage=storage, mu=w["mu"],
+                     driver=dict(alpha=w["alpha"], sigma_z=w["sigma_z"], sigma_x=w["sigma_x"],
+                                 z0=w["z0"]))
+    s.step(10)
+    o.step(10)
+    compare(s, o, ["n", "uz", "ux", "ez", "ex", "by"], TOL[storage])
+
+
+def test_full_size_wake2d_warmc_fp64():
+    """4096 x 1024 warm-closure wake, 3 steps against the oracle."""
+    w = workloads.workload("wake2d_warmc")
+    s, o = make_pair(2, w["nz"], w["nx"], delta=w["delta"], closure="warmc", dvel=w["dvel"],
+                     storage="fp64", mu=w["mu"],
+                     driver=dict(alpha=w["alpha"], sigma_z=w["sigma_z"], sigma_x=w["sigma_x"],
+                                 z0=w["z0"]))
+    s.step(3)
+    o.step(3)
+    compare(s, o, ["n", "uz", "ux", "thzz", "thxz", "ez", "ex", "by"], 1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Properties that hold at any size.
+
+def test_mirror_symmetry_full_size_lec():
+    """x -> -x symmetry of the 2048 x 512 wake after 400 steps (FP64)."""
+    w = workloads.workload("wake2d_lec_fp32")
+    from paper_2309_04872_amd.sim import Sim
+
+    s = Sim(2, w["nz"], w["nx"], delta=w["delta"], closure="lec", storage="fp64")
+    s.init_plasma(w["mu"])
+    s.init_driver(w["alpha"], w["sigma_z"], w["sigma_x"], z0=w["z0"])
+    s.step(400)
+    for q, sgn in (("n", 1), ("uz", 1), ("ux", -1)):
+        v = s.read(q)
+        assert np.abs(v - sgn * v[::-1]).max() <= 1e-11 * np.abs(v).max(), q
+    for q, sgn in (("ez", 1), ("ex", -1), ("by", -1)):
+        v = s.field(q)
+        assert np.abs(v - sgn * v[::-1]).max() <= 1e-11 * np.abs(v).max(), q
+
+
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_conservation_periodic(closure):
+    from paper_2309_04872_amd.sim import Sim
+
+    nz, nx = 256, 64
+    d = 2 * np.pi / 64
+    zz, xx = np.meshgrid(np.arange(nz), np.arange(nx))
+    s = Sim(2, nz, nx, delta=d, closure=closure, bc_z="periodic", bc_x="periodic")
+    s.init_plasma(0.03, n=1 + 0.1 * np.sin(2 * np.pi * zz / nz), uz=0.05 * np.cos(2 * np.pi * xx / nx))
+    s.init_driver(0.5, 1.0, 0.5, z0=4.0)
+    n0 = s.diagnostics()[0]
+    s.step(500)
+    dg = s.diagnostics()
+    assert dg[5] == 0
+    assert abs(dg[0] - n0) <= 1e-13 * n0
+
+
+@pytest.mark.parametrize("dims", [1, 2])
+def test_rest_state_exact(dims):
+    from paper_2309_04872_amd.sim import Sim
+
+    for closure in ("lec", "warmc"):
+        s = Sim(dims, 96, 1 if dims == 1 else 40, closure=closure)
+        s.init_plasma(0.05)
+        s.step(200)
+        for q in ("uz", "ux"):
+            assert np.all(s.read(q) == 0.0)
+        for q in ("ez", "ex", "by") if dims == 2 else ("ez",):
+            assert np.all(s.field(q) == 0.0)
+        n = s.read("n")
+        assert np.all(n == n.flat[0]) and abs(n.flat[0] - 1) <= 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Bookkeeping of the boundary: split calls, checkpoints, diagnostics, errors.
+
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+@pytest.mark.parametrize("dims", [1, 2])
+def test_split_steps_and_checkpoint_bitwise(closure, dims):
+    from paper_2309_04872_amd.sim import Sim
+
+    nz, nx = (500, 1) if dims == 1 else (80, 24)
+    d = 2 * np.pi / (128 if dims == 1 else 32)
+
+    def fresh():
+        s = Sim(dims, nz, nx, delta=d, closure=closure)
+        s.init_plasma(0.02, n=workloads.density_noise((nx, nz), 1e-3, 2))
+        s.init_driver(0.4, 0.7, 0.5, z0=4.0)
+        return s
+
+    a = fresh().step(12)
+    b = fresh().step(7)
+    blob = b.save_state()
+    b.step(5)
+    c = fresh()
+    c.load_state(blob)
+    c.step(5)
+    for q in ("n", "uz", "ux"):
+        assert np.array_equal(a.read(q), b.read(q)), q
+        assert np.array_equal(a.read(q), c.read(q)), q
+    assert np.array_equal(a.field("ez"), b.field("ez"))
+    assert np.array_equal(a.field("ez"), c.field("ez"))
+    assert c.step_count == 12
+
+
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_diagnostics_parity(closure):
+    nz, nx = 128, 32
+    d = 2 * np.pi / 32
+    s, o = make_pair(2, nz, nx, delta=d, closure=closure, mu=0.02,
+                     n=workloads.density_noise((nx, nz), 1e-2, 4),
+                     driver=dict(alpha=0.6, sigma_z=1.0, sigma_x=0.5, z0=4.0))
+    s.step(40)
+    o.step(40)
+    gd, od = s.diagnostics(), o.diagnostics()
+    assert np.allclose(gd[[0, 1, 2, 3, 4]], od[[0, 1, 2, 3, 4]], rtol=1e-9, atol=1e-14)
+    assert gd[5] == od[5] == 0 and gd[7] == od[7] == 40
+
+
+def test_read_device_matches_host():
+    from paper_2309_04872_amd.sim import Sim
+
+    s = Sim(2, 64, 16, closure="lec")
+    s.init_plasma(0.01, n=workloads.density_noise((16, 64), 1e-2, 9))
+    s.step(5)
+    import torch
+
+    dev = s.read_device("n")
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), s.read("n"))
+
+
+def test_error_paths():
+    from paper_2309_04872_amd.sim import LbwError, Sim
+
+    s = Sim(1, 64, closure="lec")
+    with pytest.raises(LbwError) as e:
+        s.step(1)
+    assert e.value.code == -6
+    with pytest.raises(LbwError) as e:
+        s.init_plasma(0.01, n=np.full(64, -1.0))
+    assert e.value.code == -5
+    s.init_plasma(0.01)
+    with pytest.raises(KeyError):
+        s.read("nope")
+    # a NaN planted in the initial scalars is reported by the diagnostics
+    A = np.zeros((2, 64))
+    A[0] = 1.0
+    A[0, 10] = np.nan
+    s.init_moments(0.01, A)
+    s.step(3)
+    with pytest.raises(LbwError) as e:
+        s.diagnostics()
+    assert e.value.code == -5
+    assert s.diagnostics(check=False)[5] > 0
