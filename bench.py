@@ -158,7 +158,8 @@ def main():
             "kernel_avg_us": k_avg_s * 1e6, "bytes_per_lu": blu, "launches": k_n,
         },
         "wall_s": wall,
-        "diagnostics": {"sum_n": dg[0], "field_energy": dg[1], "max_lattice_mach": dg[4]},
+        "diagnostics": {"sum_n": dg[0], "field_energy": dg[1], "max_lattice_mach": dg[4],
+                        "recovery_fallbacks": dg[6]},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

@@ -56,8 +56,9 @@ typedef enum {
 } lbw_status;
 
 typedef enum { LBW_LEC = 0, LBW_WARMC = 1 } lbw_closure;
-/* Population storage: FP64; FP32 (FP64 recovery); FP16 deviations
- * g = f - w_i A_ref with FP32 arithmetic (FP64 recovery). */
+/* Population storage: FP64; FP32 or FP16 deviations g = f - w_i A_ref from
+ * the uniform rest state A_ref, with FP32 collision arithmetic and FP64
+ * moment sums promoted from FP32 and FP64 closure recovery. */
 typedef enum { LBW_FP64 = 0, LBW_FP32 = 1, LBW_FP16DEV = 2 } lbw_storage;
 typedef enum { LBW_BC_OPEN = 0, LBW_BC_PERIODIC = 1 } lbw_bc;
 

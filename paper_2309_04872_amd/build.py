@@ -15,6 +15,9 @@ ARCH = os.environ.get("LBW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    # multiply-adds are fused per source expression only, so that the same
+    # expression rounds the same way in every kernel that inlines it
+    "-ffp-contract=on",
     # packed FP32 instructions stay off (they have given wrong results on this hardware)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-lambda-capture",

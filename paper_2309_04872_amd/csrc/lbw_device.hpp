@@ -52,24 +52,35 @@ template <int DIM, int CL> struct NScal {
 
 // ---------------------------------------------------------------------------
 // Population storage. Every stored value is a deviation s = f - w_q A_ref_k
-// from a per-scalar reference (A_ref = 0 for FP64 and FP32 storage); CT is
-// the arithmetic type of the collision.
+// from a per-scalar reference (A_ref = 0 for FP64 storage, the uniform rest
+// state for FP32 and FP16 storage); CT is the arithmetic type of the collision.
 template <class ST> struct Store;
+// Loads and stores take a uniform plane pointer and a 32-bit node offset.
 template <> struct Store<double> {
     using ct = double;
-    __device__ static double ld(const double *p, size_t i) { return p[i]; }
-    __device__ static void st(double *p, size_t i, double v) { p[i] = v; }
+    __device__ static double ld(const double *p, int i) { return p[i]; }
+    __device__ static void st(double *p, int i, double v) { p[i] = v; }
 };
 template <> struct Store<float> {
     using ct = float;
-    __device__ static float ld(const float *p, size_t i) { return p[i]; }
-    __device__ static void st(float *p, size_t i, float v) { p[i] = v; }
+    __device__ static float ld(const float *p, int i) { return p[i]; }
+    __device__ static void st(float *p, int i, float v) { p[i] = v; }
 };
 template <> struct Store<__half> {
     using ct = float;
-    __device__ static float ld(const __half *p, size_t i) { return __half2float(p[i]); }
-    __device__ static void st(__half *p, size_t i, float v) { p[i] = __float2half_rn(v); }
+    __device__ static float ld(const __half *p, int i) { return __half2float(p[i]); }
+    __device__ static void st(__half *p, int i, float v) { p[i] = __float2half_rn(v); }
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip. Renumber
+// them so that XCD k sweeps one contiguous band of tiles: neighbouring tiles,
+// whose halos overlap, then share one L2.
+__device__ __forceinline__ int xcd_band_tile(int b, int nblocks)
+{
+    const int x = b & 7, slot = b >> 3;
+    const int base = nblocks >> 3, rem = nblocks & 7;
+    return x * base + (x < rem ? x : rem) + slot;
+}
 
 // ---------------------------------------------------------------------------
 // Boundary indexing. Open boundaries copy the nearest bulk node (eq. open-bc);
@@ -104,87 +115,156 @@ __device__ __forceinline__ int map_stag(int i, int n, int bc)
 struct Driver {
     double alpha, sigma_z, sigma_x, z0, x0;
     double slice_zmin, slice_zmax;
+    double inv2sz2, inv2sx2;  // 1 / (2 sigma^2)
     int nslices;
     const double *slice_w;  // device
 };
 
-__device__ __forceinline__ double driver_profile(const Driver &d, double zeta)
+__device__ __forceinline__ double slice_weight(const Driver &d, double zeta)
 {
-    double s = 1.0;
-    if (d.nslices > 0) {
-        if (!(zeta >= d.slice_zmin && zeta < d.slice_zmax)) return 0.0;
-        int k = (int)floor((zeta - d.slice_zmin) / (d.slice_zmax - d.slice_zmin) * d.nslices);
-        k = k < 0 ? 0 : (k >= d.nslices ? d.nslices - 1 : k);
-        s = d.slice_w[k];
-    }
-    return d.alpha * s * exp(-zeta * zeta / (2.0 * d.sigma_z * d.sigma_z));
+    if (d.nslices <= 0) return 1.0;
+    if (!(zeta >= d.slice_zmin && zeta < d.slice_zmax)) return 0.0;
+    int k = (int)floor((zeta - d.slice_zmin) / (d.slice_zmax - d.slice_zmin) * d.nslices);
+    k = k < 0 ? 0 : (k >= d.nslices ? d.nslices - 1 : k);
+    return d.slice_w[k];
 }
 
+__device__ __forceinline__ double driver_profile(const Driver &d, double zeta)
+{
+    return d.alpha * slice_weight(d, zeta) * exp(-zeta * zeta * d.inv2sz2);
+}
+
+// n_b(z, x, t); exp(-e) is exactly zero in FP64 once e exceeds 745.2, so the
+// exponential is skipped there (most of the grid) without changing a bit.
 template <int DIM>
 __device__ __forceinline__ double driver_density(const Driver &d, double z, double x, double t)
 {
     if (d.alpha == 0.0) return 0.0;
-    double g = driver_profile(d, z - d.z0 - t);
+    const double zeta = z - d.z0 - t;
+    double e = zeta * zeta * d.inv2sz2;
     if (DIM == 2) {
-        double dx = x - d.x0;
-        g *= exp(-dx * dx / (2.0 * d.sigma_x * d.sigma_x));
+        const double dx = x - d.x0;
+        e += dx * dx * d.inv2sx2;
     }
-    return g;
+    if (e > 746.0) return 0.0;
+    return d.alpha * slice_weight(d, zeta) * exp(-e);
 }
 
 // ---------------------------------------------------------------------------
-// LEC transport-velocity recovery (Sec. 3.1). Fixed point on |p|:
-// p_{k+1} = |A_1| / (n h(n / gamma_k)), gamma_k = sqrt(1 + p_k^2),
-// h(n0) = 1 + (1 + D/2) mu n0^{2/D}; stop when |p_{k+1} - p_k| <= 1e-15 (1 + p),
-// at most 64 passes, else bisection on [0, |A_1|/n]. The vector p keeps the
-// direction of A_1. Returns false when the fallback was used.
-__device__ __forceinline__ double pow_2_over_d(double x, int dcode, double two_over_d)
-{
-    if (dcode == 1) return x * x;          // D = 1
-    if (dcode == 3) {                      // D = 3
-        double c = cbrt(x);
-        return c * c;
-    }
-    return pow(x, two_over_d);
-}
-
+// LEC transport-velocity recovery (Sec. 3.1): find |p| with
+// p (1 + a (n / gamma)^{2/D}) = P, P = |A_1| / n, gamma = sqrt(1 + p^2),
+// a = (1 + D/2) mu; the vector p keeps the direction of A_1.
+//  D = 1: the paper's fixed point p_{k+1} = P / (1 + a n^2 / (1 + p_k^2)) from
+//         p_0 = P (written without square roots), stopped when
+//         |p_{k+1} - p_k| <= 1e-15 (1 + p), at most 64 passes, else bisection on
+//         [0, P]. Several roots can exist for dense relativistic cells; the
+//         fixed point selects the one the paper's iteration reaches.
+//  D = 3: the root is unique (d/dp of the left side >= 1/3). Newton's method on
+//         d = gamma^{1/3} - 1 >= 0, where with c = 1 + d, b = a n^{2/3},
+//         S(c) = 1 + c + ... + c^5 (so that p^2 = c^6 - 1 = d S without
+//         cancellation) and h = 1 + b / c^2:
+//         G(d) = d S h^2 - P^2 = (p h)^2 - P^2 = 0, increasing in d;
+//         no root or cube root inside the loop, quadratic convergence from the
+//         lower bound p = P / (1 + b); stopped once a step falls below 1e-12 d,
+//         at most 12 passes, else bisection.
+//  other D: the fixed point with pow().
+// Returns false when a fallback was needed.
 struct LecRec {
     double uz, ux, gamma, n0, phi;  // phi = n0^{1+2/D}
 };
 
+__device__ __forceinline__ double lec_bisect(double n, double P, double a, int dcode, double two_over_d)
+{
+    double lo = 0.0, hi = P;
+    for (int k = 0; k < 200 && hi - lo > 1e-17 * (1.0 + hi); ++k) {
+        const double mid = 0.5 * (lo + hi);
+        const double g2 = 1.0 + mid * mid;
+        const double s = dcode == 1 ? n * n / g2 : pow(n / sqrt(g2), two_over_d);
+        if (mid * (1.0 + a * s) - P > 0.0) hi = mid; else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 __device__ __forceinline__ bool lec_recover(double n, double a1z, double a1x, double a_lec,
                                             int dcode, double two_over_d, LecRec &r)
 {
-    double P = sqrt(a1z * a1z + a1x * a1x) / n;
-    double p = P;
+    // |A_1| / n without squaring (squares of tiny momenta would underflow)
+    const double P = (a1x == 0.0 ? fabs(a1z) : hypot(a1z, a1x)) / n;
+    double p, g, n0, phi;
     bool ok = false;
-    for (int it = 0; it < 64; ++it) {
-        double g = sqrt(1.0 + p * p);
-        double pn = P / (1.0 + a_lec * pow_2_over_d(n / g, dcode, two_over_d));
-        double dp = pn - p;
-        p = pn;
-        if (fabs(dp) <= 1e-15 * (1.0 + pn)) {
+    if (dcode == 3) {
+        const double n23 = cbrt(n * n);
+        const double b = a_lec * n23;
+        const double P2 = P * P;
+        const double p0 = P / (1.0 + b);
+        double d = cbrt(sqrt(1.0 + p0 * p0)) - 1.0;
+        // |p| < 1e-100: gamma = 1 far below rounding, p = P / (1 + b) exactly
+        // (this also keeps subnormal P^2 out of the relative stopping test)
+        if (P < 1e-100) {
+            d = 0.0;
             ok = true;
-            break;
         }
-    }
-    if (!ok) {
-        double lo = 0.0, hi = P;
-        for (int k = 0; k < 200 && hi - lo > 1e-17 * (1.0 + hi); ++k) {
-            double mid = 0.5 * (lo + hi);
-            double g = sqrt(1.0 + mid * mid);
-            double res = mid * (1.0 + a_lec * pow_2_over_d(n / g, dcode, two_over_d)) - P;
-            if (res > 0.0) hi = mid; else lo = mid;
+        for (int it = 0; it < 12 && !ok; ++it) {
+            const double c = 1.0 + d, ic = 1.0 / c;
+            const double S = 1.0 + c * (1.0 + c * (1.0 + c * (1.0 + c * (1.0 + c))));
+            const double dS = 1.0 + c * (2.0 + c * (3.0 + c * (4.0 + 5.0 * c)));
+            const double h = 1.0 + b * ic * ic;          // 1 + a (n / gamma)^{2/3}
+            const double G = d * S * h * h - P2;          // (p h)^2 - P^2, increasing in d
+            const double dG = (S + d * dS) * h * h - 4.0 * d * S * h * b * ic * ic * ic;
+            double dn = d - G / dG;
+            if (dn < 0.0) dn = 0.0;
+            const double step = fabs(dn - d);
+            d = dn;
+            // quadratic convergence: after a step below 1e-12 d the iterate is
+            // exact to rounding (a tighter test would chase rounding noise in G)
+            if (step <= 1e-12 * d || step == 0.0) {
+                ok = true;
+                break;
+            }
         }
-        p = 0.5 * (lo + hi);
+        const double c = 1.0 + d, c2 = c * c;
+        const double S = 1.0 + c * (1.0 + c * (1.0 + c * (1.0 + c * (1.0 + c))));
+        if (ok && P < 1e-100) {
+            p = p0;
+            g = 1.0;
+            n0 = n;
+            phi = n0 * n23;
+        } else if (ok) {
+            p = sqrt(d * S);
+            g = c2 * c;
+            n0 = n / g;
+            phi = n0 * (n23 / c2);
+        } else {
+            p = lec_bisect(n, P, a_lec, dcode, two_over_d);
+            g = sqrt(1.0 + p * p);
+            n0 = n / g;
+            phi = n0 * cbrt(n0 * n0);
+        }
+    } else {
+        const double an2 = dcode == 1 ? a_lec * n * n : 0.0;
+        p = P;
+        for (int it = 0; it < 64; ++it) {
+            const double g2 = 1.0 + p * p;
+            const double pn = dcode == 1 ? P * g2 / (g2 + an2)
+                                         : P / (1.0 + a_lec * pow(n / sqrt(g2), two_over_d));
+            const double dp = pn - p;
+            p = pn;
+            if (fabs(dp) <= 1e-15 * (1.0 + pn)) {
+                ok = true;
+                break;
+            }
+        }
+        if (!ok) p = lec_bisect(n, P, a_lec, dcode, two_over_d);
+        g = sqrt(1.0 + p * p);
+        n0 = n / g;
+        phi = dcode == 1 ? n0 * n0 * n0 : n0 * pow(n0, two_over_d);
     }
-    double g = sqrt(1.0 + p * p);
-    double scale = P > 0.0 ? p / (P * n * g) : 0.0;  // u = p_vec / gamma, p_vec = A_1 p / (n P)
+    const double scale = P > 0.0 ? p / (P * n * g) : 0.0;  // u = p_vec / gamma
     r.uz = a1z * scale;
     r.ux = a1x * scale;
     r.gamma = g;
-    r.n0 = n / g;
-    r.phi = r.n0 * pow_2_over_d(r.n0, dcode, two_over_d);
+    r.n0 = n0;
+    r.phi = phi;
     return ok;
 }
 

@@ -13,6 +13,8 @@
 
 #include "lbw_device.hpp"
 
+#include <type_traits>
+
 namespace lbw {
 
 constexpr int NLAG2 = 5;  // theta^00, theta^0z, theta^0x, lambda u_z, lambda u_x
@@ -36,39 +38,56 @@ struct StepArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Collision of one scalar in deviation form (A_ref = 0 gives the plain form):
-// s*_q = (1 - omega) s_q + omega w_q (dA + A P_q) + dt w_q F,
+// Collision of all scalars in deviation form (A_ref = 0 gives the plain form):
+// s*_{k,q} = (1 - omega) s_{k,q} + w_q (omega dA_k + dt F_k + omega A_k P_q),
 // P_q = 3 (e_q.u)/Lambda + 9/2 (e_q.u)^2/Lambda^2 - 3/2 u^2/Lambda^2, which is
-// f_eq_q / (w_q A) - 1 of eq. ade-feq with nu^2 = Lambda^2 / 3.
-template <int DIM, class CT>
-__device__ __forceinline__ void collide_scalar(CT *s, CT dA, CT A, CT uz, CT ux, CT c1, CT c2,
-                                               CT c3uu, CT omega, CT dtF)
+// f_eq_q / (w_q A) - 1 of eq. ade-feq with nu^2 = Lambda^2 / 3; P_q is shared
+// by every scalar since they all move with the same u (Sec. 3.1, Sec. 4.1).
+template <int DIM, int K, class CT>
+__device__ __forceinline__ void collide_all(CT (*s)[Lattice<DIM>::Q], const double *A,
+                                            const double *aref, const double *F, double uz,
+                                            double ux, double lam, double omega, double dt)
 {
     using L = Lattice<DIM>;
+    constexpr int Q = L::Q;
+    const CT uzc = (CT)uz, uxc = (CT)ux;
+    const CT c1 = (CT)(3.0 / lam), c2 = (CT)(4.5 / (lam * lam));
+    const CT c3uu = (CT)(1.5 * (uz * uz + ux * ux) / (lam * lam));
+    CT P[Q];
 #pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-        const CT w = (CT)L::w(q);
-        const CT eu = uz * (CT)L::ez(q) + ux * (CT)L::ex(q);
-        const CT P = c1 * eu + c2 * eu * eu - c3uu;
-        s[q] = ((CT)1 - omega) * s[q] + omega * w * (dA + A * P) + w * dtF;
+    for (int q = 0; q < Q; ++q) {
+        const CT eu = uzc * (CT)L::ez(q) + uxc * (CT)L::ex(q);
+        P[q] = c1 * eu + c2 * eu * eu - c3uu;
+    }
+    const CT om = (CT)omega, keep = (CT)(1.0 - omega);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const CT al = (CT)(omega * (A[k] - aref[k]) + dt * F[k]);
+        const CT be = (CT)(omega * A[k]);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s[k][q] = keep * s[k][q] + (CT)L::w(q) * (al + be * P[q]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// 2D fused step. Tile TZ x TX nodes per workgroup (one node per thread);
-// recovery on the tile plus a one-node ring (LDS), fields on a two-node halo.
-template <int CL, class ST, int TZ, int TX>
-__global__ __launch_bounds__(TZ *TX) void k_step2d(StepArgs a)
+// 2D fused step. Tile TZ x TX nodes per workgroup, CPT nodes per thread (rows
+// lx, lx + TX/CPT, ...: every thread issues the loads of all its nodes before
+// it waits on any). Recovery runs on the tile plus a one-node ring (LDS), the
+// Yee update on a two-node field halo (LDS).
+template <int CL, class ST, int TZ, int TX, int CPT>
+__global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 {
     using L = Lattice<2>;
     using CT = typename Store<ST>::ct;
     constexpr int Q = L::Q;
     constexpr int K = NScal<2, CL>::K;
-    constexpr int NT = TZ * TX;
+    constexpr int NT = TZ * TX / CPT;
+    constexpr int XS = TX / CPT;             // row stride between a thread's nodes
     constexpr int RZ = TZ + 2, RX = TX + 2;  // recovery region (ring of 1)
     constexpr int FZ = TZ + 4, FX = TX + 4;  // field region (halo of 2)
     constexpr int NG = CL == LEC ? 1 : 7;    // gradient quantities
     constexpr int NRING = 2 * RZ + 2 * TX;
+    static_assert(TX % CPT == 0, "tile rows must split evenly over a thread's nodes");
 
     __shared__ double s_ez[FX][FZ], s_ex[FX][FZ], s_by[FX][FZ], s_bn[FX][FZ];
     __shared__ double s_jz[RX][RZ], s_jx[RX][RZ];
@@ -77,17 +96,11 @@ __global__ __launch_bounds__(TZ *TX) void k_step2d(StepArgs a)
     const int tid = threadIdx.x;
     const int nz = a.nz, nx = a.nx, bcz = a.bcz, bcx = a.bcx;
     const size_t nc = (size_t)a.ncell;
-    const int z0 = blockIdx.x * TZ, x0 = blockIdx.y * TX;
+    const int ntz = (nz + TZ - 1) / TZ;
+    const int tile = xcd_band_tile(blockIdx.x, gridDim.x);
+    const int z0 = (tile % ntz) * TZ, x0 = (tile / ntz) * TX;
     const ST *src = (const ST *)a.src;
     ST *dst = (ST *)a.dst;
-
-    // local coordinates of a global (unwrapped) coordinate after the boundary rule
-    auto fzn = [&](int g) { return map_node(g, nz, bcz) - (z0 - 2); };
-    auto fzs = [&](int g) { return map_stag(g, nz, bcz) - (z0 - 2); };
-    auto fxn = [&](int g) { return map_node(g, nx, bcx) - (x0 - 2); };
-    auto fxs = [&](int g) { return map_stag(g, nx, bcx) - (x0 - 2); };
-    auto rzn = [&](int g) { return map_node(g, nz, bcz) - (z0 - 1); };
-    auto rxn = [&](int g) { return map_node(g, nx, bcx) - (x0 - 1); };
 
     // ---- 1. old fields into LDS (E^{n-1}, B^{n-3/2}; or E^n, B^{n-1/2})
     for (int p = tid; p < FZ * FX; p += NT) {
@@ -103,16 +116,24 @@ __global__ __launch_bounds__(TZ *TX) void k_step2d(StepArgs a)
 #pragma unroll
     for (int k = 0; k < K; ++k) aref[k] = a.aref[k];
 
-    // pull the K x Q populations of node (gz, gx) and return the FP64 moments
-    auto pull = [&](int gz, int gx, CT (*s)[Q], double *A) {
+    // source node of direction q: (gx - e_x, gz - e_z) when streaming
+    auto load = [&](int gz, int gx, CT (*s)[Q]) {
+        const int sh = a.do_pull ? 1 : 0;
+        int zs[3], xs[3];
+#pragma unroll
+        for (int e = -1; e <= 1; ++e) {
+            zs[e + 1] = fix_node(gz - sh * e, nz, bcz);
+            xs[e + 1] = fix_node(gx - sh * e, nx, bcx) * nz;
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int sz = a.do_pull ? gz - L::ez(q) : gz;
-            const int sx = a.do_pull ? gx - L::ex(q) : gx;
-            const size_t c = (size_t)fix_node(sx, nx, bcx) * nz + fix_node(sz, nz, bcz);
+            const int c = xs[L::ex(q) + 1] + zs[L::ez(q) + 1];
 #pragma unroll
-            for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src, (size_t)(k * Q + q) * nc + c);
+            for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
         }
+    };
+    // zeroth moments in the storage type, promoted to FP64 (eq. disc-moments-ade)
+    auto moments = [&](CT (*s)[Q], double *A) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             CT acc = 0;
@@ -151,137 +172,165 @@ __global__ __launch_bounds__(TZ *TX) void k_step2d(StepArgs a)
     };
 
     // ---- 2. ring nodes: pull, recover, keep only the LDS results
-    if (tid < NRING) {
+    for (int t = tid; t < NRING; t += NT) {
         int rz, rx;
-        if (tid < RZ) { rz = tid; rx = 0; }
-        else if (tid < 2 * RZ) { rz = tid - RZ; rx = RX - 1; }
-        else { const int s = tid - 2 * RZ; rx = 1 + s / 2; rz = (s & 1) ? RZ - 1 : 0; }
+        if (t < RZ) { rz = t; rx = 0; }
+        else if (t < 2 * RZ) { rz = t - RZ; rx = RX - 1; }
+        else { const int u = t - 2 * RZ; rx = 1 + u / 2; rz = (u & 1) ? RZ - 1 : 0; }
         CT sr[K][Q];
         double Ar[K];
-        pull(z0 - 1 + rz, x0 - 1 + rx, sr, Ar);
+        load(z0 - 1 + rz, x0 - 1 + rx, sr);
+        moments(sr, Ar);
         double uzr, uxr;
         recover_to_lds(Ar, rz, rx, uzr, uxr);
     }
 
-    // ---- 3. own node: pull, recover, keep populations in registers
-    const int lz = tid % TZ, lx = tid / TZ;
-    const int gz = z0 + lz, gx = x0 + lx;
-    const bool active = gz < nz && gx < nx;
-    CT s[K][Q];
-    double A[K];
-    pull(gz, gx, s, A);
-    double uz, ux;
-    recover_to_lds(A, lz + 1, lx + 1, uz, ux);
+    // ---- 3. own nodes: pull all of them, then recover; populations stay in registers
+    const int lz = tid % TZ, lxb = tid / TZ;
+    const int gz = z0 + lz;
+    CT s[CPT][K][Q];
+    double A[CPT][K];
+    double uz[CPT], ux[CPT];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) load(gz, x0 + lxb + r * XS, s[r]);
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) {
+        moments(s[r], A[r]);
+        recover_to_lds(A[r], lz + 1, lxb + r * XS + 1, uz[r], ux[r]);
+    }
     __syncthreads();
 
-    const double dt = a.dt, hdt = 0.5 * a.dt, id = 1.0 / a.delta;
-    // ---- 4. finish the Yee update of the previous step with J^n
-    if (a.do_maxwell) {
-        for (int p = tid; p < (FZ - 1) * (FX - 1); p += NT) {
-            const int fz = p % (FZ - 1), fx = p / (FZ - 1);
+    // Stages 4-6 read LDS through the boundary rule; tiles that touch no open
+    // boundary (and every periodic direction) compile it away: their LDS
+    // accesses are plain offsets from the thread's own slot.
+    const bool edge = (bcz == BC_OPEN && (z0 < 2 || z0 + TZ + 3 > nz)) ||
+                      (bcx == BC_OPEN && (x0 < 2 || x0 + TX + 3 > nx));
+    auto rest = [&](auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
+        // local coordinates of a global (unwrapped) coordinate after the boundary rule
+        auto fzn = [&](int g) { return (EDGE ? map_node(g, nz, bcz) : g) - (z0 - 2); };
+        auto fzs = [&](int g) { return (EDGE ? map_stag(g, nz, bcz) : g) - (z0 - 2); };
+        auto fxn = [&](int g) { return (EDGE ? map_node(g, nx, bcx) : g) - (x0 - 2); };
+        auto fxs = [&](int g) { return (EDGE ? map_stag(g, nx, bcx) : g) - (x0 - 2); };
+        auto rzn = [&](int g) { return (EDGE ? map_node(g, nz, bcz) : g) - (z0 - 1); };
+        auto rxn = [&](int g) { return (EDGE ? map_node(g, nx, bcx) : g) - (x0 - 1); };
+        const double dt = a.dt, hdt = 0.5 * a.dt, id = 1.0 / a.delta;
+        // ---- 4. finish the Yee update of the previous step with J^n
+        if (a.do_maxwell) {
+            for (int p = tid; p < (FZ - 1) * (FX - 1); p += NT) {
+                const int fz = p % (FZ - 1), fx = p / (FZ - 1);
+                const int gzz = z0 - 2 + fz, gxx = x0 - 2 + fx;
+                const double curl = ((s_ex[fxs(gxx)][fzn(gzz + 1)] - s_ex[fxs(gxx)][fzn(gzz)]) -
+                                     (s_ez[fxn(gxx + 1)][fzs(gzz)] - s_ez[fxn(gxx)][fzs(gzz)])) * id;
+                const double b1 = s_by[fx][fz] - hdt * curl;  // B^{n-1}
+                s_by[fx][fz] = b1 - hdt * curl;               // B^{n-1/2}
+            }
+            __syncthreads();
+            const double th = (a.step - 0.5) * dt;
+            for (int p = tid; p < (FZ - 2) * (FX - 2); p += NT) {
+                const int fz = 1 + p % (FZ - 2), fx = 1 + p / (FZ - 2);
+                const int gzz = z0 - 2 + fz, gxx = x0 - 2 + fx;
+                if (fx <= FX - 3) {  // E_x at (z_gzz, x_{gxx+1/2})
+                    const double jx = 0.5 * (s_jx[rxn(gxx)][rzn(gzz)] + s_jx[rxn(gxx + 1)][rzn(gzz)]);
+                    const double cx = -(s_by[fxs(gxx)][fzs(gzz)] - s_by[fxs(gxx)][fzs(gzz - 1)]) * id;
+                    s_ex[fx][fz] = s_ex[fx][fz] + dt * (cx - jx);
+                }
+                if (fz <= FZ - 3) {  // E_z at (z_{gzz+1/2}, x_gxx)
+                    const double jz = 0.5 * (s_jz[rxn(gxx)][rzn(gzz)] + s_jz[rxn(gxx)][rzn(gzz + 1)]);
+                    const double jb = -driver_density<2>(a.drv, (gzz + 0.5) * a.delta,
+                                                         (gxx - 0.5 * (nx - 1)) * a.delta, th);
+                    const double cz = (s_by[fxs(gxx)][fzs(gzz)] - s_by[fxs(gxx - 1)][fzs(gzz)]) * id;
+                    s_ez[fx][fz] = s_ez[fx][fz] + dt * (cz - jz - jb);
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- 5. B^n = B^{n-1/2} - dt/2 curl E^n around the tile; write E^n, B^{n-1/2}
+        for (int p = tid; p < (FZ - 3) * (FX - 3); p += NT) {
+            const int fz = 1 + p % (FZ - 3), fx = 1 + p / (FZ - 3);
             const int gzz = z0 - 2 + fz, gxx = x0 - 2 + fx;
             const double curl = ((s_ex[fxs(gxx)][fzn(gzz + 1)] - s_ex[fxs(gxx)][fzn(gzz)]) -
                                  (s_ez[fxn(gxx + 1)][fzs(gzz)] - s_ez[fxn(gxx)][fzs(gzz)])) * id;
-            const double b1 = s_by[fx][fz] - hdt * curl;  // B^{n-1}
-            s_by[fx][fz] = b1 - hdt * curl;               // B^{n-1/2}
+            s_bn[fx][fz] = s_by[fx][fz] - hdt * curl;
         }
-        __syncthreads();
-        const double th = (a.step - 0.5) * dt;
-        for (int p = tid; p < (FZ - 2) * (FX - 2); p += NT) {
-            const int fz = 1 + p % (FZ - 2), fx = 1 + p / (FZ - 2);
-            const int gzz = z0 - 2 + fz, gxx = x0 - 2 + fx;
-            if (fx <= FX - 3) {  // E_x at (z_gzz, x_{gxx+1/2})
-                const double jx = 0.5 * (s_jx[rxn(gxx)][rzn(gzz)] + s_jx[rxn(gxx + 1)][rzn(gzz)]);
-                const double cx = -(s_by[fxs(gxx)][fzs(gzz)] - s_by[fxs(gxx)][fzs(gzz - 1)]) * id;
-                s_ex[fx][fz] = s_ex[fx][fz] + dt * (cx - jx);
-            }
-            if (fz <= FZ - 3) {  // E_z at (z_{gzz+1/2}, x_gxx)
-                const double jz = 0.5 * (s_jz[rxn(gxx)][rzn(gzz)] + s_jz[rxn(gxx)][rzn(gzz + 1)]);
-                const double jb = -driver_density<2>(a.drv, (gzz + 0.5) * a.delta,
-                                                     (gxx - 0.5 * (nx - 1)) * a.delta, th);
-                const double cz = (s_by[fxs(gxx)][fzs(gzz)] - s_by[fxs(gxx - 1)][fzs(gzz)]) * id;
-                s_ez[fx][fz] = s_ez[fx][fz] + dt * (cz - jz - jb);
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
+            const int lx = lxb + r * XS, gx = x0 + lx;
+            if (gz < nz && gx < nx) {
+                const size_t c = (size_t)gx * nz + gz;
+                a.ez_out[c] = s_ez[lx + 2][lz + 2];
+                a.ex_out[c] = s_ex[lx + 2][lz + 2];
+                a.by_out[c] = s_by[lx + 2][lz + 2];
             }
         }
         __syncthreads();
-    }
 
-    // ---- 5. B^n = B^{n-1/2} - dt/2 curl E^n around the tile; write E^n, B^{n-1/2}
-    for (int p = tid; p < (FZ - 3) * (FX - 3); p += NT) {
-        const int fz = 1 + p % (FZ - 3), fx = 1 + p / (FZ - 3);
-        const int gzz = z0 - 2 + fz, gxx = x0 - 2 + fx;
-        const double curl = ((s_ex[fxs(gxx)][fzn(gzz + 1)] - s_ex[fxs(gxx)][fzn(gzz)]) -
-                             (s_ez[fxn(gxx + 1)][fzs(gzz)] - s_ez[fxn(gxx)][fzs(gzz)])) * id;
-        s_bn[fx][fz] = s_by[fx][fz] - hdt * curl;
-    }
-    if (active) {
-        const size_t c = (size_t)gx * nz + gz;
-        a.ez_out[c] = s_ez[lx + 2][lz + 2];
-        a.ex_out[c] = s_ex[lx + 2][lz + 2];
-        a.by_out[c] = s_by[lx + 2][lz + 2];
-    }
-    __syncthreads();
-    if (!active) return;
-
-    // ---- 6. node fields, forcing, collision
-    const double Ez = 0.5 * (s_ez[fxn(gx)][fzs(gz - 1)] + s_ez[fxn(gx)][fzs(gz)]);
-    const double Ex = 0.5 * (s_ex[fxs(gx - 1)][fzn(gz)] + s_ex[fxs(gx)][fzn(gz)]);
-    const double By = 0.25 * (s_bn[fxs(gx)][fzs(gz)] + s_bn[fxs(gx)][fzs(gz - 1)] +
-                              s_bn[fxs(gx - 1)][fzs(gz)] + s_bn[fxs(gx - 1)][fzs(gz - 1)]);
-    const int rzc = lz + 1, rxc = lx + 1;
-    const int rzp = rzn(gz + 1), rzm = rzn(gz - 1), rxp = rxn(gx + 1), rxm = rxn(gx - 1);
-    auto Dz = [&](int g) { return (s_g[g][rxc][rzp] - s_g[g][rxc][rzm]) * a.inv2d; };
-    auto Dx = [&](int g) { return (s_g[g][rxp][rzc] - s_g[g][rxm][rzc]) * a.inv2d; };
-    const double n = A[0];
-    double F[K];
-    const size_t c = (size_t)gx * nz + gz;
-    if constexpr (CL == LEC) {
-        // eq. lb-ade-lec-comps-F (q = -1): F = -mu grad n0^{1+2/D} - n (E + u x B)
-        F[0] = 0.0;
-        F[1] = -a.mu * Dz(0) - n * (Ez + ux * By);
-        F[2] = -a.mu * Dx(0) - n * (Ex - uz * By);
-    } else {
-        // App. A warm-closure right-hand sides, Cartesian slab (r -> x, phi -> y)
-        const double th0z = s_g[0][rxc][rzc], th0x = s_g[1][rxc][rzc];
-        const double thzz = s_g[2][rxc][rzc], thxx = s_g[3][rxc][rzc];
-        const double thxz = s_g[4][rxc][rzc];
-        const double luz = s_g[5][rxc][rzc], lux = s_g[6][rxc][rzc];
-        const double th00 = ux * th0x + uz * th0z;
-        double l00, l0z, l0x, lluz, llux;
-        if (a.lag_init) {
-            l00 = th00; l0z = th0z; l0x = th0x; lluz = luz; llux = lux;
-        } else {
-            l00 = a.lag[0 * nc + c]; l0z = a.lag[1 * nc + c]; l0x = a.lag[2 * nc + c];
-            lluz = a.lag[3 * nc + c]; llux = a.lag[4 * nc + c];
+        // ---- 6. node fields, forcing, collision
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
+            const int lx = lxb + r * XS, gx = x0 + lx;
+            if (!(gz < nz && gx < nx)) continue;
+            const double Ez = 0.5 * (s_ez[fxn(gx)][fzs(gz - 1)] + s_ez[fxn(gx)][fzs(gz)]);
+            const double Ex = 0.5 * (s_ex[fxs(gx - 1)][fzn(gz)] + s_ex[fxs(gx)][fzn(gz)]);
+            const double By = 0.25 * (s_bn[fxs(gx)][fzs(gz)] + s_bn[fxs(gx)][fzs(gz - 1)] +
+                                      s_bn[fxs(gx - 1)][fzs(gz)] + s_bn[fxs(gx - 1)][fzs(gz - 1)]);
+            const int rzc = lz + 1, rxc = lx + 1;
+            const int rzp = rzn(gz + 1), rzm = rzn(gz - 1), rxp = rxn(gx + 1), rxm = rxn(gx - 1);
+            auto Dz = [&](int g) { return (s_g[g][rxc][rzp] - s_g[g][rxc][rzm]) * a.inv2d; };
+            auto Dx = [&](int g) { return (s_g[g][rxp][rzc] - s_g[g][rxm][rzc]) * a.inv2d; };
+            const double n = A[r][0], vz = uz[r], vx = ux[r];
+            double F[K];
+            const size_t c = (size_t)gx * nz + gz;
+            if constexpr (CL == LEC) {
+                // eq. lb-ade-lec-comps-F (q = -1): F = -mu grad n0^{1+2/D} - n (E + u x B)
+                F[0] = 0.0;
+                F[1] = -a.mu * Dz(0) - n * (Ez + vx * By);
+                F[2] = -a.mu * Dx(0) - n * (Ex - vz * By);
+            } else {
+                // App. A warm-closure right-hand sides, Cartesian slab (r -> x, phi -> y)
+                const double th0z = s_g[0][rxc][rzc], th0x = s_g[1][rxc][rzc];
+                const double thzz = s_g[2][rxc][rzc], thxx = s_g[3][rxc][rzc];
+                const double thxz = s_g[4][rxc][rzc];
+                const double luz = s_g[5][rxc][rzc], lux = s_g[6][rxc][rzc];
+                const double th00 = vx * th0x + vz * th0z;
+                double l00, l0z, l0x, lluz, llux;
+                if (a.lag_init) {
+                    l00 = th00; l0z = th0z; l0x = th0x; lluz = luz; llux = lux;
+                } else {
+                    l00 = a.lag[0 * nc + c]; l0z = a.lag[1 * nc + c]; l0x = a.lag[2 * nc + c];
+                    lluz = a.lag[3 * nc + c]; llux = a.lag[4 * nc + c];
+                }
+                a.lag[0 * nc + c] = th00; a.lag[1 * nc + c] = th0z; a.lag[2 * nc + c] = th0x;
+                a.lag[3 * nc + c] = luz; a.lag[4 * nc + c] = lux;
+                const double idt = 1.0 / dt;
+                const double dt00 = (th00 - l00) * idt, dt0z = (th0z - l0z) * idt;
+                const double dt0x = (th0x - l0x) * idt;
+                const double dtluz = (luz - lluz) * idt, dtlux = (lux - llux) * idt;
+                F[0] = 0.0;
+                F[1] = -dt00 - Dx(1) - Dz(0) - n * (Ex * vx + Ez * vz);
+                F[2] = -dt0z - Dx(4) - Dz(2) - n * (Ez + vx * By);
+                F[3] = -dt0x - Dx(3) - Dz(4) - n * (Ex - vz * By);
+                F[4] = -2.0 * th0z * dtluz - 2.0 * thxz * Dx(5) - 2.0 * thzz * Dz(5) -
+                       2.0 * (Ez * th0z + By * thxz);
+                F[5] = -2.0 * th0x * dtlux - 2.0 * thxx * Dx(6) - 2.0 * thxz * Dz(6) -
+                       2.0 * (Ex * th0x - By * thxz);
+                F[6] = 0.0;
+                F[7] = -th0z * dtlux - th0x * dtluz - thxz * Dx(6) - thxx * Dx(5) - thzz * Dz(6) -
+                       thxz * Dz(5) - (Ex * th0z + Ez * th0x + By * (thxx - thzz));
+            }
+            collide_all<2, K, CT>(s[r], A[r], aref, F, vz, vx, a.lam, a.omega, dt);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                    Store<ST>::st(dst + (size_t)(k * Q + q) * nc, (int)c, s[r][k][q]);
         }
-        a.lag[0 * nc + c] = th00; a.lag[1 * nc + c] = th0z; a.lag[2 * nc + c] = th0x;
-        a.lag[3 * nc + c] = luz; a.lag[4 * nc + c] = lux;
-        const double idt = 1.0 / dt;
-        const double dt00 = (th00 - l00) * idt, dt0z = (th0z - l0z) * idt, dt0x = (th0x - l0x) * idt;
-        const double dtluz = (luz - lluz) * idt, dtlux = (lux - llux) * idt;
-        F[0] = 0.0;
-        F[1] = -dt00 - Dx(1) - Dz(0) - n * (Ex * ux + Ez * uz);
-        F[2] = -dt0z - Dx(4) - Dz(2) - n * (Ez + ux * By);
-        F[3] = -dt0x - Dx(3) - Dz(4) - n * (Ex - uz * By);
-        F[4] = -2.0 * th0z * dtluz - 2.0 * thxz * Dx(5) - 2.0 * thzz * Dz(5) -
-               2.0 * (Ez * th0z + By * thxz);
-        F[5] = -2.0 * th0x * dtlux - 2.0 * thxx * Dx(6) - 2.0 * thxz * Dz(6) -
-               2.0 * (Ex * th0x - By * thxz);
-        F[6] = 0.0;
-        F[7] = -th0z * dtlux - th0x * dtluz - thxz * Dx(6) - thxx * Dx(5) - thzz * Dz(6) -
-               thxz * Dz(5) - (Ex * th0z + Ez * th0x + By * (thxx - thzz));
-    }
-    const CT lam = (CT)a.lam;
-    const CT c1 = (CT)3 / lam, c2 = (CT)4.5 / (lam * lam);
-    const CT c3uu = (CT)(1.5 * (uz * uz + ux * ux) / (a.lam * a.lam));
-    const CT om = (CT)a.omega;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        collide_scalar<2, CT>(s[k], (CT)(A[k] - aref[k]), (CT)A[k], (CT)uz, (CT)ux, c1, c2, c3uu,
-                              om, (CT)(dt * F[k]));
-#pragma unroll
-        for (int q = 0; q < Q; ++q) Store<ST>::st(dst, (size_t)(k * Q + q) * nc + c, s[k][q]);
-    }
+    };
+    if (edge)
+        rest(std::true_type{});
+    else
+        rest(std::false_type{});
 }
 
 // ---------------------------------------------------------------------------
@@ -312,9 +361,9 @@ __global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int sz = a.do_pull ? gz - L::ez(q) : gz;
-            const size_t c = (size_t)fix_node(sz, nz, bcz);
+            const int c = fix_node(sz, nz, bcz);
 #pragma unroll
-            for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src, (size_t)(k * Q + q) * nc + c);
+            for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -391,17 +440,11 @@ __global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
         F[2] = -(th0z - l0z) * idt - Dz(1) - n * Ez;
         F[3] = -2.0 * th0z * ((luz - lluz) * idt) - 2.0 * thzz * Dz(2) - 2.0 * (Ez * th0z);
     }
-    const CT lam = (CT)a.lam;
-    const CT c1 = (CT)3 / lam, c2 = (CT)4.5 / (lam * lam);
-    const CT c3uu = (CT)(1.5 * uz * uz / (a.lam * a.lam));
-    const CT om = (CT)a.omega;
+    collide_all<1, K, CT>(s, A, aref, F, uz, 0.0, a.lam, a.omega, dt);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        collide_scalar<1, CT>(s[k], (CT)(A[k] - aref[k]), (CT)A[k], (CT)uz, (CT)0, c1, c2, c3uu,
-                              om, (CT)(dt * F[k]));
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) Store<ST>::st(dst, (size_t)(k * Q + q) * nc + c, s[k][q]);
-    }
+        for (int q = 0; q < Q; ++q) Store<ST>::st(dst + (size_t)(k * Q + q) * nc, (int)c, s[k][q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,9 +468,9 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
         typename Store<ST>::ct acc = 0;
         for (int q = 0; q < Q; ++q) {
             const int sz = gz - L::ez(q), sx = gx - L::ex(q);
-            const size_t c = (size_t)fix_node(sx, a.nx, a.bcx) * a.nz + fix_node(sz, a.nz, a.bcz);
-            const typename Store<ST>::ct v = Store<ST>::ld(src, (size_t)(k * Q + q) * nc + c);
-            Store<ST>::st(dst, (size_t)(k * Q + q) * nc + idx, v);
+            const int c = fix_node(sx, a.nx, a.bcx) * a.nz + fix_node(sz, a.nz, a.bcz);
+            const typename Store<ST>::ct v = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
+            Store<ST>::st(dst + (size_t)(k * Q + q) * nc, idx, v);
             acc += v;
         }
         A[k] = a.aref[k] + (double)acc;
@@ -510,7 +553,7 @@ __global__ void k_init_pops(void *dst_, const double *A, const double *uzv, cons
             const double eu = uz * L::ez(q) + ux * L::ex(q);
             const double P = 3.0 * eu / lam + 4.5 * eu * eu / (lam * lam) - 1.5 * uu / (lam * lam);
             const double w = L::w(q);
-            Store<ST>::st(dst, (size_t)(k * Q + q) * nc + idx,
+            Store<ST>::st(dst + (size_t)(k * Q + q) * nc, idx,
                           (typename Store<ST>::ct)(w * (Ak - aref[k]) + w * Ak * P));
         }
     }
@@ -530,7 +573,7 @@ __global__ void k_read_moment(StepArgs a, int which, double *out)
     double A[K];
     for (int k = 0; k < K; ++k) {
         typename Store<ST>::ct acc = 0;
-        for (int q = 0; q < Q; ++q) acc += Store<ST>::ld(src, (size_t)(k * Q + q) * nc + idx);
+        for (int q = 0; q < Q; ++q) acc += Store<ST>::ld(src + (size_t)(k * Q + q) * nc, idx);
         A[k] = a.aref[k] + (double)acc;
     }
     const double n = A[0];
@@ -591,7 +634,11 @@ __global__ void k_read_field(StepArgs a, int which, int at_nodes, double *out)
     auto EX = [&](int jj, int ii) { return a.ex_in[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
     auto BH = [&](int jj, int ii) { return a.by_in[(size_t)fix_stag(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
     const double hdt = 0.5 * a.dt, id = 1.0 / a.delta;
+    // B^n at a staggered slot: the copy rule picks the real slot first, then
+    // the curl is taken there
     auto BN = [&](int jj, int ii) {
+        jj = fix_stag(jj, nx, bx);
+        ii = fix_stag(ii, nz, bz);
         const double curl = ((EX(jj, ii + 1) - EX(jj, ii)) - (EZ(jj + 1, ii) - EZ(jj, ii))) * id;
         return BH(jj, ii) - hdt * curl;
     };
@@ -628,7 +675,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, double *part)
         double A[K];
         for (int k = 0; k < K; ++k) {
             typename Store<ST>::ct acc = 0;
-            for (int q = 0; q < Q; ++q) acc += Store<ST>::ld(src, (size_t)(k * Q + q) * nc + idx);
+            for (int q = 0; q < Q; ++q) acc += Store<ST>::ld(src + (size_t)(k * Q + q) * nc, idx);
             A[k] = a.aref[k] + (double)acc;
         }
         const double n = A[0];

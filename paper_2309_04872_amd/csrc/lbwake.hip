@@ -17,8 +17,42 @@ using namespace lbw;
 
 namespace {
 
-constexpr int TZ2 = 32, TX2 = 8;  // 2D tile (nodes along z, x)
-constexpr int TZ1 = 256;          // 1D tile
+// Tile shapes (nodes along z x x per workgroup) and nodes per thread of the 2D
+// step, per closure and storage; the build may override them for sweeps.
+#ifndef LBW_TZ2
+#define LBW_TZ2 64
+#endif
+#ifndef LBW_TX2
+#define LBW_TX2 8
+#endif
+#ifndef LBW_CPT2
+#define LBW_CPT2 1
+#endif
+#ifndef LBW_TZ2_F64
+#define LBW_TZ2_F64 64
+#endif
+#ifndef LBW_TX2_F64
+#define LBW_TX2_F64 4
+#endif
+#ifndef LBW_TZ2_W
+#define LBW_TZ2_W 64
+#endif
+#ifndef LBW_TX2_W
+#define LBW_TX2_W 4
+#endif
+#ifndef LBW_TZ1
+#define LBW_TZ1 256
+#endif
+template <int CL, class ST> struct Tile2 {  // local-equilibrium, FP32 / FP16 storage
+    static constexpr int TZ = LBW_TZ2, TX = LBW_TX2, CPT = LBW_CPT2;
+};
+template <> struct Tile2<LEC, double> {
+    static constexpr int TZ = LBW_TZ2_F64, TX = LBW_TX2_F64, CPT = 1;
+};
+template <class ST> struct Tile2<WARMC, ST> {
+    static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1;
+};
+constexpr int TZ1 = LBW_TZ1;  // 1D tile
 constexpr int MAX_SLICES = 4096;
 constexpr size_t ALIGN = 256;
 
@@ -158,8 +192,11 @@ template <int DIM, int CL, class ST> struct Impl {
     static void step(const StepArgs &a, hipStream_t st)
     {
         if constexpr (DIM == 2) {
-            dim3 grid((a.nz + TZ2 - 1) / TZ2, (a.nx + TX2 - 1) / TX2);
-            hipLaunchKernelGGL((k_step2d<CL, ST, TZ2, TX2>), grid, dim3(TZ2 * TX2), 0, st, a);
+            // one-dimensional grid: the kernel maps blocks to tiles XCD by XCD
+            using T = Tile2<CL, ST>;
+            dim3 grid(((a.nz + T::TZ - 1) / T::TZ) * ((a.nx + T::TX - 1) / T::TX));
+            hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT>), grid,
+                               dim3(T::TZ * T::TX / T::CPT), 0, st, a);
         } else {
             dim3 grid((a.nz + TZ1 - 1) / TZ1);
             hipLaunchKernelGGL((k_step1d<CL, ST, TZ1>), grid, dim3(TZ1), 0, st, a);
@@ -224,14 +261,15 @@ Ops ops_for(const lbw_grid_desc &g)
 
 double lambda_rest(double mu, double D) { return 0.5 * (D * mu + std::sqrt(D * D * mu * mu + 4.0)); }
 
-// Storage reference A_ref per scalar: zero for FP64 / FP32 storage; the rest
-// state for FP16 deviations (n = 1, lambda_0, lambda_0 mu on the populated
-// pressure diagonal, zero momenta).
+// Storage reference A_ref per scalar: zero for FP64 storage; for FP32 and
+// FP16 storage the uniform rest state (n = 1, lambda_0, lambda_0 mu on the
+// populated pressure diagonal, zero momenta), so that a quiet region stores
+// values near zero and its rounding does not add up coherently over steps.
 void fill_aref(lbw_sim *s)
 {
     const lbw_grid_desc &g = s->g;
     for (int k = 0; k < 8; ++k) s->aref_host[k] = 0.0;
-    if (g.storage != LBW_FP16DEV) return;
+    if (g.storage == LBW_FP64) return;
     s->aref_host[0] = 1.0;
     if (g.closure == LBW_WARMC) {
         const double l0 = lambda_rest(s->mu, g.dvel);
@@ -476,6 +514,8 @@ lbw_status lbw_init_driver(lbw_sim *s, const lbw_driver_desc *d, int init_fields
     v.slice_zmin = d->slice_zmin;
     v.slice_zmax = d->slice_zmax;
     v.slice_w = (const double *)(s->ws + s->L.slice);
+    v.inv2sz2 = d->sigma_z > 0 ? 1.0 / (2.0 * d->sigma_z * d->sigma_z) : 0.0;
+    v.inv2sx2 = d->sigma_x > 0 ? 1.0 / (2.0 * d->sigma_x * d->sigma_x) : 0.0;
     if (d->nslices > 0)
         HIPCHK(s, hipMemcpyAsync(s->ws + s->L.slice, d->slice_w, d->nslices * sizeof(double),
                                  hipMemcpyHostToDevice, s->stream));

@@ -62,6 +62,7 @@ def compare(s, o, quantities, tol, report=None, slice_=None):
         worst[q] = e
     if report is not None:
         report.update(worst)
+    print("rel-L2", {q: float("%.3g" % e) for q, e in worst.items()}, flush=True)
     bad = {q: e for q, e in worst.items() if not e <= tol}
     assert not bad, f"relative L2 above {tol}: {bad}"
     return worst

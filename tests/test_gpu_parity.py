@@ -272,3 +272,49 @@ def test_error_paths():
         s.diagnostics()
     assert e.value.code == -5
     assert s.diagnostics(check=False)[5] > 0
+
+
+@pytest.mark.parametrize("dims,D", [(1, 1.0), (2, 3.0), (1, 3.0)])
+def test_lec_recovery_random_states(dims, D):
+    """The kernels' closure recovery (Sec. 3.1) on random relativistic states
+    against the oracle's fixed point, through lbw_init_moments + lbw_read_moment."""
+    import oracle
+    from paper_2309_04872_amd.sim import Sim
+
+    rng = np.random.default_rng(21)
+    nz, nx = (2048, 1) if dims == 1 else (64, 32)
+    for mu in (1e-4, 1e-2, 0.1):
+        n = rng.uniform(0.2, 3.0 if D == 3.0 else 2.0, size=(nx, nz))
+        p = rng.uniform(-3, 3, size=(2, nx, nz))
+        # also tiny momenta (Gaussian tails ahead of a bunch) and, for D = 3,
+        # strongly relativistic ones
+        p[:, :, : nz // 8] *= 10.0 ** rng.uniform(-200, -5, size=(nx, nz // 8))
+        if D == 3.0:
+            p[:, :, nz // 8: nz // 4] *= 15.0
+        if dims == 1:
+            p[1] = 0.0
+        g = np.sqrt(1 + (p ** 2).sum(0))
+        h = 1 + (1 + D / 2) * mu * (n / g) ** (2 / D)
+        A = [n, h * n * p[0]] + ([h * n * p[1]] if dims == 2 else [])
+        s = Sim(dims, nz, nx, closure="lec", dvel=D)
+        s.init_moments(mu, np.array(A))
+        uz, gam = s.read("uz"), s.read("gamma")
+        flat = lambda v: np.ravel(v)
+        ref = np.array([oracle.lec_recover(nn, az, ax, D, mu) for nn, az, ax in
+                        zip(flat(n), flat(A[1]), flat(A[2]) if dims == 2 else np.zeros(n.size))])
+        eu = np.abs(flat(uz) - ref[:, 0])
+        assert eu.max() <= 1e-13, ("uz vs oracle", eu.max(), mu)
+        # gamma against the exact sqrt(1 + p^2); the oracle's 1/sqrt(1 - u^2)
+        # itself carries a relative error ~ eps gamma^2
+        eg = np.abs(flat(gam) - flat(g)) / flat(g)
+        assert eg.max() <= 1e-13, ("gamma", eg.max(), mu)
+        eo = np.abs(flat(gam) - ref[:, 2]) / ref[:, 2]
+        assert np.all(eo <= 1e-13 + 4e-16 * ref[:, 2] ** 2), ("gamma vs oracle", eo.max(), mu)
+        assert np.abs(flat(uz) - flat(p[0] / g)).max() <= 1e-13
+        tiny = np.abs(flat(p[0])) < 1e-6
+        et = np.abs(flat(uz)[tiny] - ref[tiny, 0]) / np.maximum(np.abs(ref[tiny, 0]), 1e-300)
+        assert et.max() <= 1e-13, ("tiny uz relative", et.max(), mu, flat(uz)[tiny][np.argmax(et)],
+                                   ref[tiny, 0][np.argmax(et)])
+        if dims == 2:
+            assert np.abs(flat(s.read("ux")) - ref[:, 1]).max() <= 1e-13
+        assert s.diagnostics()[6] == 0  # no recovery fallback
