@@ -39,10 +39,17 @@ def bytes_per_lu(dims, closure, storage):
     return 2 * K * Q * sb + 2 * nf * 8 + 2 * nlag * 8
 
 
-# Measured once on the GPU machine with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on
-# the fused kernel of this workload (see profiles/); None until measured or
-# after the kernel changed.
-TRAFFIC_BYTES_PER_LAUNCH = {}
+# HBM-side bytes per launch of the fused kernel, measured with rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE on the GPU machine and scaled by a 1 GiB copy
+# (the summaries and commands are in profiles/k_step2d_*.md). Valid for the
+# kernel as profiled; remove an entry when the kernel changes.
+TRAFFIC_BYTES_PER_LAUNCH = {
+    ("wake2d_lec_fp32", "fp32"): 302.1e6,
+    ("wake2d_lec_fp32", "fp64"): 622.3e6,
+    ("wake2d_warmc", "fp64"): 7238.8e6,
+    ("wake2d_warmc", "fp32"): 3922.0e6,
+    ("wake2d_warmc", "fp16dev"): 2111.7e6,
+}
 
 
 def cpu_baseline(w, budget_s=12.0):
@@ -120,7 +127,8 @@ def main():
     wall = time.perf_counter() - t0
     ms_total = ev0.elapsed_time(ev1)
     dg = s.diagnostics()
-    # kernel duration: same workload again with an event pair around every launch
+    # kernel duration: the same workload again, one event pair around the
+    # back-to-back fused launches (HIP events on the simulation's stream)
     s.init_plasma(w["mu"], n=workloads.initial_density(w) if w.get("noise") else None)
     s.init_driver(w["alpha"], w["sigma_z"], w["sigma_x"], z0=w["z0"])
     s.set_timing(True)

@@ -169,10 +169,11 @@ lbw_status lbw_diagnostics(lbw_sim *sim, double *out);
 
 long lbw_step_count(const lbw_sim *sim);
 
-/* Kernel timing: while enabled, lbw_step brackets every fused step launch
- * with a pair of HIP events on the simulation's stream; lbw_get_timing
- * returns the summed kernel time (ms) and the number of launches since the
- * last enable (it synchronises the stream). Off by default. */
+/* Kernel timing: while enabled, lbw_step brackets its back-to-back fused
+ * step launches (not the closing canonicalisation) with a pair of HIP events
+ * on the simulation's stream; lbw_get_timing returns the summed time (ms) of
+ * those batches and the number of fused launches since the last enable (it
+ * synchronises the stream). Off by default. */
 lbw_status lbw_set_timing(lbw_sim *sim, int enable);
 lbw_status lbw_get_timing(lbw_sim *sim, double *kernel_ms, long *launches);
 

@@ -130,7 +130,7 @@ struct lbw_sim {
     std::vector<hipEvent_t> ev;
     int ev_used;
     double kernel_ms;
-    long launches;
+    long launches, pending_launches;
 };
 
 static lbw_status fail(lbw_sim *s, lbw_status code, const std::string &m)
@@ -321,6 +321,7 @@ lbw_status lbw_create(const lbw_grid_desc *grid, void *ws, size_t ws_bytes, void
     s->ev_used = 0;
     s->kernel_ms = 0.0;
     s->launches = 0;
+    s->pending_launches = 0;
     *out = s;
     return LBW_OK;
 }
@@ -340,8 +341,9 @@ static lbw_status drain_timing(lbw_sim *s)
         float ms = 0.0f;
         HIPCHK(s, hipEventElapsedTime(&ms, s->ev[i], s->ev[i + 1]));
         s->kernel_ms += ms;
-        s->launches += 1;
     }
+    s->launches += s->pending_launches;
+    s->pending_launches = 0;
     s->ev_used = 0;
     return LBW_OK;
 }
@@ -352,7 +354,7 @@ lbw_status lbw_set_timing(lbw_sim *s, int enable)
     lbw_status st = drain_timing(s);
     if (st != LBW_OK) return st;
     if (enable && s->ev.empty()) {
-        s->ev.resize(2048);
+        s->ev.resize(256);
         for (auto &e : s->ev) HIPCHK(s, hipEventCreate(&e));
     }
     s->timing = enable != 0;
@@ -558,23 +560,20 @@ lbw_status lbw_step(lbw_sim *s, int nsteps)
     if (nsteps < 0) return fail(s, LBW_ERR_ARG, "nsteps must be >= 0");
     if (nsteps == 0) return LBW_OK;
     const Ops ops = ops_for(s->g);
+    if (s->timing) {
+        if (s->ev_used + 2 > (int)s->ev.size()) {
+            lbw_status st = drain_timing(s);
+            if (st != LBW_OK) return st;
+        }
+        HIPCHK(s, hipEventRecord(s->ev[s->ev_used++], s->stream));
+    }
     for (int t = 0; t < nsteps; ++t) {
         StepArgs a = base_args(s);
         set_io(s, a);
         a.do_pull = s->canonical ? 0 : 1;
         a.do_maxwell = s->canonical ? 0 : 1;
         a.lag_init = s->lag_valid ? 0 : 1;
-        if (s->timing) {
-            if (s->ev_used + 2 > (int)s->ev.size()) {
-                lbw_status st = drain_timing(s);
-                if (st != LBW_OK) return st;
-            }
-            HIPCHK(s, hipEventRecord(s->ev[s->ev_used++], s->stream));
-            ops.step(a, s->stream);
-            HIPCHK(s, hipEventRecord(s->ev[s->ev_used++], s->stream));
-        } else {
-            ops.step(a, s->stream);
-        }
+        ops.step(a, s->stream);
         s->pcur ^= 1;
         s->fcur ^= 1;
         s->canonical = false;
@@ -582,6 +581,10 @@ lbw_status lbw_step(lbw_sim *s, int nsteps)
         s->step++;
     }
     HIPCHK(s, hipGetLastError());
+    if (s->timing) {
+        HIPCHK(s, hipEventRecord(s->ev[s->ev_used++], s->stream));
+        s->pending_launches += nsteps;
+    }
     // bring the state to canonical form (f^n, E^n, B^{n-1/2})
     StepArgs a = base_args(s);
     set_io(s, a);
