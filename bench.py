@@ -40,7 +40,7 @@ def bytes_per_lu(dims, closure, storage):
 
 
 # HBM-side bytes per launch of the fused kernel, measured with rocprofv3
-# --pmc FETCH_SIZE and WRITE_SIZE on the GPU machine and scaled by a 1 GiB copy
+# --pmc FETCH_SIZE and WRITE_SIZE and scaled by a 1 GiB copy
 # (the summaries and commands are in profiles/k_step2d_*.md). Valid for the
 # kernel as profiled; remove an entry when the kernel changes.
 TRAFFIC_BYTES_PER_LAUNCH = {
@@ -77,6 +77,99 @@ def cpu_baseline(w, budget_s=12.0):
             "sample": f"full {w['nx']}x{w['nz']} grid, {n} FP64 steps ({dt:.1f} s) of the same workload"}
 
 
+def batch_bytes_per_step(insts):
+    """Algorithmic bytes of one step of the batched scan: per instance
+    bytes_per_lu(1, closure, FP64) times its node count."""
+    return sum(d["nz"] * bytes_per_lu(1, d["closure"], "fp64") for d in insts)
+
+
+def cpu_baseline_batch(insts, budget_s=12.0):
+    """The CPU oracle on a bounded sample of the scan: its first instances in
+    turn (alternating closures), 256 steps each, until the budget is spent."""
+    import oracle
+
+    cells_steps = 0
+    used = []
+    t0 = time.perf_counter()
+    for d in insts:
+        o = oracle.Oracle(1, d["nz"], 1, delta=d["delta"], dt=d["dt"], tau_tilde=d["tau_tilde"],
+                          closure=0 if d["closure"] == "lec" else 1, dvel=d["dvel"], mu=d["mu"],
+                          alpha=d["alpha"], sigma_z=d["sigma_z"], z0=d["z0"])
+        o.init()
+        o.step(256)
+        cells_steps += d["nz"] * 256
+        used.append(d["nz"])
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": cells_steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {len(used)} instances of the scan ({sum(used)} nodes), 256 FP64 steps each, "
+                      f"{dt:.1f} s"}
+
+
+def bench_batch(args):
+    import torch
+
+    from paper_2309_04872_amd import workloads
+    from paper_2309_04872_amd.batch import Batch
+
+    insts = workloads.batch_instances()
+    steps = args.steps if args.steps is not None else workloads.BATCH_SCAN["steps"]
+    cells = sum(d["nz"] for d in insts)
+    b = Batch(insts).init()
+    threads, cpt = b.autotune(probe_steps=20)
+    if args.warmup:
+        b.step(args.warmup, graph=True)
+    torch.cuda.synchronize()
+    b.init()  # timed region: the scan from t = 0, inputs resident in HBM
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(b.stream)
+    t0 = time.perf_counter()
+    b.step(steps, graph=True)
+    ev1.record(b.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    k_ms = b.last_ms()  # HIP events on the batch's stream around the one launch
+    bad = b.nonfinite()
+    bps = batch_bytes_per_step(insts)
+    achieved = bps * steps / (k_ms / 1e3) / 1e9
+    line = {
+        "metric": "MLUPS (LB+field)",
+        "value": cells * steps / (ms_total / 1e3) / 1e6,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_total / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch1d_scan", "instances": len(insts), "total_nodes": cells,
+            "nz_range": [min(d["nz"] for d in insts), max(d["nz"] for d in insts)],
+            "closures": "alternating lec / warmc", "populations": "fp64", "delta": "lambda_p/128",
+            "steps_per_run": steps, "launches": 1, "hip_graph": True,
+            "autotuned": {"threads": threads, "nodes_per_thread": cpt}, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch1d",
+            "kernel_avg_us": k_ms * 1e3, "bytes_per_step": bps, "launches": 1,
+        },
+        "wall_s": wall,
+        "diagnostics": {"nonfinite_instances": int((bad > 0).sum())},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_batch(insts, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +184,9 @@ def main():
         print(f"bench.py runs on one GPU only (the scheme is built and measured per GPU); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch1d_scan":
+        return bench_batch(args)
 
     import torch
 

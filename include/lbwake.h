@@ -52,7 +52,7 @@ typedef enum {
     LBW_ERR_UNSTABLE = -4,   /* tau~ <= 1/2 or Courant number too large */
     LBW_ERR_NONFINITE = -5,  /* NaN or Inf found in the state */
     LBW_ERR_STATE = -6,      /* call out of order (e.g. step before init) */
-    LBW_ERR_UNSUPPORTED = -7 /* valid request this build does not implement */
+    LBW_ERR_UNSUPPORTED = -7 /* valid request the library does not implement */
 } lbw_status;
 
 typedef enum { LBW_LEC = 0, LBW_WARMC = 1 } lbw_closure;
@@ -181,6 +181,90 @@ lbw_status lbw_get_timing(lbw_sim *sim, double *kernel_ms, long *launches);
 size_t lbw_state_bytes(const lbw_sim *sim);
 lbw_status lbw_save_state(lbw_sim *sim, void *host, size_t bytes);
 lbw_status lbw_load_state(lbw_sim *sim, const void *host, size_t bytes);
+
+/* ---------------------------------------------------------------------------
+ * Batched 1D parameter scans (one launch for many independent 1D runs).
+ *
+ * A batch holds ninst independent 1D simulations ("instances") of their own
+ * length, closure, temperature, time step and driver, all with FP64
+ * populations on the D1Q3 stencil. Each instance follows exactly the 1D step
+ * of lbw_step (Sec. 2.1-2.2 streaming and collision, Sec. 3.1 / Sec. 4.1
+ * recoveries and forces, Sec. 5 field update and driver); the instances only
+ * share the launch. lbw_batch_step runs all requested steps of every
+ * instance inside one persistent kernel launch: one workgroup owns one
+ * instance for the whole launch and separates consecutive steps with a
+ * workgroup barrier, so no instance ever waits on another and the launch
+ * needs no co-residency. Workgroups take instances longest first.
+ *
+ * The workspace is caller-owned device memory (256-byte aligned) of at least
+ * lbw_batch_workspace_bytes(); the library allocates no device memory. It
+ * holds, per instance, two population buffers (K x 3 planes of the padded
+ * length, K = 2 for LEC and 4 for WARMC), E_z, the warm closure's three
+ * lagged values, a snapshot of the state used by the autotuner, and the
+ * instance's parameters, step counter and non-finite count.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int nz;            /* nodes, >= 4 */
+    int closure;       /* lbw_closure */
+    double dvel;       /* D: velocity dimensions of the closure (eq. temp-scaling, eq. traces3) */
+    double mu;         /* k_B T / (m c^2) of the uniform plasma, >= 0 */
+    double delta;      /* grid spacing in units of c / omega_p */
+    double dt;         /* time step, 0 < dt <= delta */
+    double tau_tilde;  /* dimensionless relaxation time, > 1/2 */
+    int bc;            /* lbw_bc along z */
+    double alpha;      /* driver peak density n_b / n_0 (0: no driver) */
+    double sigma_z;    /* driver rms length, > 0 when alpha != 0 */
+    double z0;         /* driver centre at t = 0 */
+} lbw_instance_desc;
+
+/* E_z (on the nodes, as lbw_read_field gives it in 1D) for lbw_batch_read. */
+#define LBW_BATCH_EZ 100
+
+typedef struct lbw_batch lbw_batch;
+
+/* Workspace bytes for this set of instances; 0 if a descriptor is invalid. */
+size_t lbw_batch_workspace_bytes(const lbw_instance_desc *inst, int ninst);
+/* Validates the descriptors (as lbw_create), copies them to the device and
+ * returns a handle. Returns LBW_ERR_ARG for an invalid descriptor or
+ * ninst outside [1, 65536], LBW_ERR_UNSTABLE for tau_tilde <= 1/2 or
+ * dt > delta, LBW_ERR_WORKSPACE for a short or misaligned workspace. */
+lbw_status lbw_batch_create(const lbw_instance_desc *inst, int ninst, void *device_workspace,
+                            size_t workspace_bytes, void *hip_stream, lbw_batch **out);
+/* Every instance to the uniform plasma at rest at its temperature with the
+ * causal field of its driver (as lbw_init_plasma + lbw_init_driver with
+ * init_fields = 1). n_init (host, nullable): the densities of all instances
+ * concatenated in instance order (sum of nz values), positive and finite.
+ * Synchronises the stream. */
+lbw_status lbw_batch_init(lbw_batch *b, const double *n_init);
+/* Advance every instance by nsteps steps in one persistent kernel launch,
+ * ending on the canonical state (f^n, E^n). use_graph = 1 launches it from a
+ * HIP graph captured on first use for this (nsteps, configuration). Returns
+ * without synchronising. */
+lbw_status lbw_batch_step(lbw_batch *b, int nsteps, int use_graph);
+/* Launch configuration of the persistent kernel: threads per workgroup and
+ * nodes per thread per pass, one of (256, 1), (256, 2), (512, 1), (512, 2),
+ * (1024, 1); the default is (1024, 1). LBW_ERR_ARG for any other pair. */
+lbw_status lbw_batch_set_config(lbw_batch *b, int threads, int nodes_per_thread);
+lbw_status lbw_batch_get_config(const lbw_batch *b, int *threads, int *nodes_per_thread);
+/* Autotuner: runs probe_steps steps under every configuration from the same
+ * state (snapshot and restore inside the workspace), keeps the fastest and
+ * returns it. The state afterwards is bit-for-bit the state before.
+ * Synchronises the stream. */
+lbw_status lbw_batch_autotune(lbw_batch *b, int probe_steps, int *threads, int *nodes_per_thread);
+/* One observable of instance inst into host_out (count = that instance's
+ * nz): an lbw_moment, or LBW_BATCH_EZ. Synchronises the stream. */
+lbw_status lbw_batch_read(lbw_batch *b, int inst, int which, double *host_out, size_t count);
+/* Per instance, the number of nodes whose density, velocity or E_z was not
+ * finite at the end of the last lbw_batch_step (ninst ints, host).
+ * Synchronises the stream. */
+lbw_status lbw_batch_nonfinite(lbw_batch *b, int *counts);
+/* Steps taken since lbw_batch_init (the same for every instance). */
+long lbw_batch_step_count(const lbw_batch *b);
+/* Duration in ms of the last lbw_batch_step launch (HIP events on the
+ * batch's stream around it). Synchronises on the end event. */
+lbw_status lbw_batch_get_timing(lbw_batch *b, double *ms_last_step);
+const char *lbw_batch_last_error(const lbw_batch *b);
+void lbw_batch_destroy(lbw_batch *b);
 
 const char *lbw_last_error(const lbw_sim *sim);
 const char *lbw_version(void);

@@ -28,7 +28,12 @@ EXPORTS = [
     "lbw_set_field", "lbw_step", "lbw_read_moment", "lbw_read_moment_device", "lbw_read_field",
     "lbw_diagnostics", "lbw_step_count", "lbw_set_timing", "lbw_get_timing", "lbw_state_bytes", "lbw_save_state", "lbw_load_state",
     "lbw_last_error", "lbw_version", "lbw_destroy",
+    "lbw_batch_workspace_bytes", "lbw_batch_create", "lbw_batch_init", "lbw_batch_step",
+    "lbw_batch_set_config", "lbw_batch_get_config", "lbw_batch_autotune", "lbw_batch_read",
+    "lbw_batch_nonfinite", "lbw_batch_step_count", "lbw_batch_get_timing", "lbw_batch_last_error",
+    "lbw_batch_destroy",
 ]
+BATCH_EZ = 100
 
 
 class GridDesc(ctypes.Structure):
@@ -41,6 +46,15 @@ class GridDesc(ctypes.Structure):
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [
+        ("nz", ctypes.c_int), ("closure", ctypes.c_int), ("dvel", ctypes.c_double),
+        ("mu", ctypes.c_double), ("delta", ctypes.c_double), ("dt", ctypes.c_double),
+        ("tau_tilde", ctypes.c_double), ("bc", ctypes.c_int), ("alpha", ctypes.c_double),
+        ("sigma_z", ctypes.c_double), ("z0", ctypes.c_double),
+    ]
 
 
 class PlasmaDesc(ctypes.Structure):
@@ -113,6 +127,34 @@ def load(path: str | None = None):
     L.lbw_version.argtypes = []
     L.lbw_destroy.restype = None
     L.lbw_destroy.argtypes = [vp]
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.lbw_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.lbw_batch_workspace_bytes.argtypes = [ctypes.POINTER(InstanceDesc), ctypes.c_int]
+    L.lbw_batch_create.restype = ctypes.c_int
+    L.lbw_batch_create.argtypes = [ctypes.POINTER(InstanceDesc), ctypes.c_int, vp, ctypes.c_size_t, vp,
+                                   ctypes.POINTER(vp)]
+    L.lbw_batch_init.restype = ctypes.c_int
+    L.lbw_batch_init.argtypes = [vp, _dp]
+    L.lbw_batch_step.restype = ctypes.c_int
+    L.lbw_batch_step.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.lbw_batch_set_config.restype = ctypes.c_int
+    L.lbw_batch_set_config.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.lbw_batch_get_config.restype = ctypes.c_int
+    L.lbw_batch_get_config.argtypes = [vp, ip, ip]
+    L.lbw_batch_autotune.restype = ctypes.c_int
+    L.lbw_batch_autotune.argtypes = [vp, ctypes.c_int, ip, ip]
+    L.lbw_batch_read.restype = ctypes.c_int
+    L.lbw_batch_read.argtypes = [vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_size_t]
+    L.lbw_batch_nonfinite.restype = ctypes.c_int
+    L.lbw_batch_nonfinite.argtypes = [vp, ip]
+    L.lbw_batch_step_count.restype = ctypes.c_long
+    L.lbw_batch_step_count.argtypes = [vp]
+    L.lbw_batch_get_timing.restype = ctypes.c_int
+    L.lbw_batch_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.lbw_batch_last_error.restype = ctypes.c_char_p
+    L.lbw_batch_last_error.argtypes = [vp]
+    L.lbw_batch_destroy.restype = None
+    L.lbw_batch_destroy.argtypes = [vp]
     if path is None:
         _LIB = L
     return L

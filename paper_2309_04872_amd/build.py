@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "lbwake.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "lbw_kernels.hpp"), os.path.join(HERE, "csrc", "lbw_device.hpp"),
+SRCS = [SRC, os.path.join(HERE, "csrc", "lbw_batch.hip")]
+DEPS = [*SRCS, os.path.join(HERE, "csrc", "lbw_kernels.hpp"), os.path.join(HERE, "csrc", "lbw_device.hpp"),
         os.path.join(ROOT, "include", "lbwake.h")]
 SO = os.path.join(HERE, "liblbwake.so")
 ARCH = os.environ.get("LBW_OFFLOAD_ARCH", "gfx950")
@@ -25,11 +26,11 @@ HIPCC_FLAGS = [
 
 
 def build(force: bool = True, verbose: bool = False) -> str:
-    """Compile ``csrc/lbwake.hip`` into ``liblbwake.so``; always recompiles when force."""
+    """Compile the HIP sources under ``csrc/`` into ``liblbwake.so``; always recompiles when force."""
     if not force and os.path.exists(SO) and all(os.path.getmtime(SO) >= os.path.getmtime(d) for d in DEPS):
         return SO
     tmp = SO + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, SRC, "-o", tmp]
+    cmd = ["hipcc", *HIPCC_FLAGS, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

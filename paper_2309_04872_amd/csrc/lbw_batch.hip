@@ -1,0 +1,768 @@
+// lbw_batch.hip -- batched 1D parameter scans: many independent 1D runs of
+// the moment-matching LB wake scheme advanced by one persistent launch.
+//
+// One workgroup owns one instance for the whole launch. It sweeps its nodes
+// in passes of (threads x nodes-per-thread) nodes, separates time steps with a
+// workgroup barrier and finishes on the canonical state (f^n, E^n) inside the
+// same launch. The per-node arithmetic is the 1D fused step of
+// lbw_kernels.hpp: pull streaming (Sec. 2.1, eq. open-bc), moments, LEC
+// (Sec. 3.1) or WARMC (Sec. 4.1) recovery, forces, the E_z update from the
+// plasma and bunch currents (Sec. 5) and the BGK collision with the source of
+// eq. lsource. Everything an instance needs between launches (buffer parity,
+// step counter, whether its lagged values exist) lives in device memory, so a
+// launch has no per-call argument but the step count and can be replayed from
+// a HIP graph.
+#include "../../include/lbwake.h"
+#include "lbw_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace lbw;
+
+namespace {
+
+constexpr int MAX_INST = 65536;
+constexpr int PAD = 64;  // node padding of every plane (one wavefront)
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Per-instance constants (device, read-only in the step kernel).
+struct BInst {
+    int nz, nzp, closure, bc, dcode, K;
+    size_t pop, fld, lag;  // element offsets of its populations, E_z, lagged values
+    double delta, dt, inv2d, omega, lam, mu, a_lec, two_over_d, dvel;
+    Driver drv;
+};
+
+// Per-instance mutable state (device); written only by the instance's own
+// workgroup at the end of a launch.
+struct BState {
+    long step;      // steps taken
+    int cur;        // population buffer holding the canonical f^n
+    int lag_valid;  // warm closure lagged values exist
+    int nonfinite;  // non-finite nodes at the end of the last launch
+    int pad[3];
+};
+
+struct BatchArgs {
+    const BInst *inst;
+    const int *order;  // workgroup -> instance, longest first
+    double *pop0, *pop1, *ez, *lag;
+    BState *st;
+    int nsteps;
+};
+
+// LDS for the recovered quantities whose z-derivatives the forces need:
+// LEC phi | WARMC theta^0z, theta^zz, lambda u_z, on the pass plus one node
+// on each side.
+template <int T, int CPT> struct Lds {
+    double g[3][T * CPT + 2];
+    int bad;
+};
+
+template <int CL> struct Node1 {
+    static constexpr int K = NScal<1, CL>::K;
+    double s[K][3];
+    double A[K];
+    double uz;
+    WarmRec w;
+};
+
+template <int CL>
+__device__ __forceinline__ void pull_node(const BInst &P, const double *src, int gz, bool do_pull,
+                                          Node1<CL> &nd)
+{
+    using L = Lattice<1>;
+    constexpr int K = NScal<1, CL>::K;
+    const size_t nzp = (size_t)P.nzp;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int c = fix_node(do_pull ? gz - L::ez(q) : gz, P.nz, P.bc);
+#pragma unroll
+        for (int k = 0; k < K; ++k) nd.s[k][q] = src[(size_t)(k * 3 + q) * nzp + c];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc += nd.s[k][q];
+        nd.A[k] = 0.0 + acc;
+    }
+}
+
+// Recovery of one node; writes the quantities the forces differentiate into
+// LDS slot r.
+template <int CL, int T, int CPT>
+__device__ __forceinline__ void recover_node(const BInst &P, Node1<CL> &nd, Lds<T, CPT> &sh, int r)
+{
+    if constexpr (CL == LEC) {
+        LecRec l;
+        lec_recover(nd.A[0], nd.A[1], 0.0, P.a_lec, P.dcode, P.two_over_d, l);
+        nd.uz = l.uz;
+        sh.g[0][r] = l.phi;
+    } else {
+        warm_recover<1>(nd.A, nd.w);
+        nd.uz = nd.w.uz;
+        sh.g[0][r] = nd.w.th0z;
+        sh.g[1][r] = nd.w.thzz;
+        sh.g[2][r] = nd.w.luz;
+    }
+}
+
+// One pass of the fused step over nodes [base, base + T*CPT) of one instance.
+template <int CL, int T, int CPT>
+__device__ __forceinline__ void step_pass(const BInst &P, const double *src, double *dst, double *ez,
+                                          double *lag, int base, bool do_pull, bool do_maxwell,
+                                          bool lag_init, long step, Lds<T, CPT> &sh)
+{
+    constexpr int K = NScal<1, CL>::K;
+    constexpr int W = T * CPT;
+    const int tid = threadIdx.x;
+    const int nz = P.nz;
+    const size_t nzp = (size_t)P.nzp;
+    if (tid < 2) {
+        Node1<CL> h;
+        const int r = tid == 0 ? 0 : W + 1;
+        pull_node<CL>(P, src, base - 1 + r, do_pull, h);
+        recover_node<CL, T, CPT>(P, h, sh, r);
+    }
+    Node1<CL> nd[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) pull_node<CL>(P, src, base + tid + j * T, do_pull, nd[j]);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) recover_node<CL, T, CPT>(P, nd[j], sh, 1 + tid + j * T);
+    __syncthreads();
+    const double dt = P.dt;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int gz = base + tid + j * T;
+        if (gz >= nz) continue;
+        Node1<CL> &v = nd[j];
+        const double n = v.A[0], uz = v.uz;
+        double Ez = ez[gz];
+        if (do_maxwell) {
+            const double jb = driver_density<1>(P.drv, gz * P.delta, 0.0, (step - 0.5) * dt);
+            Ez = Ez + dt * (n * uz + jb);
+        }
+        ez[gz] = Ez;
+        const int rp = map_node(gz + 1, nz, P.bc) - (base - 1);
+        const int rm = map_node(gz - 1, nz, P.bc) - (base - 1);
+        auto Dz = [&](int g) { return (sh.g[g][rp] - sh.g[g][rm]) * P.inv2d; };
+        double F[K];
+        if constexpr (CL == LEC) {
+            F[0] = 0.0;
+            F[1] = -P.mu * Dz(0) - n * Ez;
+        } else {
+            const double th0z = v.w.th0z, thzz = v.w.thzz, luz = v.w.luz, th00 = v.w.th00;
+            double l00, l0z, lluz;
+            if (lag_init) {
+                l00 = th00; l0z = th0z; lluz = luz;
+            } else {
+                l00 = lag[0 * nzp + gz]; l0z = lag[1 * nzp + gz]; lluz = lag[2 * nzp + gz];
+            }
+            lag[0 * nzp + gz] = th00; lag[1 * nzp + gz] = th0z; lag[2 * nzp + gz] = luz;
+            const double idt = 1.0 / dt;
+            F[0] = 0.0;
+            F[1] = -(th00 - l00) * idt - Dz(0) - n * (Ez * uz);
+            F[2] = -(th0z - l0z) * idt - Dz(1) - n * Ez;
+            F[3] = -2.0 * th0z * ((luz - lluz) * idt) - 2.0 * thzz * Dz(2) - 2.0 * (Ez * th0z);
+        }
+        const double zero[K] = {};
+        collide_all<1, K, double>(v.s, v.A, zero, F, uz, 0.0, P.lam, P.omega, dt);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + gz] = v.s[k][q];
+    }
+    __syncthreads();  // the next pass reuses the LDS slots
+}
+
+// Finish: stream f*^{n-1} into f^n, E^n = E^{n-1} + dt (n u + n_b) at
+// t^{n-1/2}; returns the number of non-finite nodes this thread saw.
+template <int CL, int T, int CPT>
+__device__ __forceinline__ int finish_pass(const BInst &P, const double *src, double *dst, double *ez,
+                                           int base, long step)
+{
+    constexpr int K = NScal<1, CL>::K;
+    const size_t nzp = (size_t)P.nzp;
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int gz = base + threadIdx.x + j * T;
+        if (gz >= P.nz) continue;
+        Node1<CL> v;
+        pull_node<CL>(P, src, gz, true, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + gz] = v.s[k][q];
+        double uz;
+        if constexpr (CL == LEC) {
+            LecRec l;
+            lec_recover(v.A[0], v.A[1], 0.0, P.a_lec, P.dcode, P.two_over_d, l);
+            uz = l.uz;
+        } else {
+            warm_recover<1>(v.A, v.w);
+            uz = v.w.uz;
+        }
+        const double jb = driver_density<1>(P.drv, gz * P.delta, 0.0, (step - 0.5) * P.dt);
+        const double e = ez[gz] + P.dt * (v.A[0] * uz + jb);
+        ez[gz] = e;
+        if (!isfinite(v.A[0]) || !isfinite(uz) || !isfinite(e)) ++bad;
+    }
+    return bad;
+}
+
+template <int CL, int T, int CPT>
+__device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds<T, CPT> &sh)
+{
+    constexpr int W = T * CPT;
+    const int nsteps = a.nsteps;
+    int cur = st->cur;
+    const long step0 = st->step;
+    const bool lag_init = st->lag_valid == 0;
+    double *pop[2] = {a.pop0 + P.pop, a.pop1 + P.pop};
+    double *ez = a.ez + P.fld;
+    double *lag = CL == WARMC ? a.lag + P.lag : nullptr;
+    for (int s = 0; s < nsteps; ++s) {
+        const bool from_canonical = s == 0;
+        for (int base = 0; base < P.nz; base += W)
+            step_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez, lag, base, !from_canonical,
+                                  !from_canonical, from_canonical && lag_init, step0 + s, sh);
+        cur ^= 1;
+        // step_pass ends on a barrier: every store of this step is visible to
+        // the whole workgroup before the next step reads its neighbours
+    }
+    if (threadIdx.x == 0) sh.bad = 0;
+    __syncthreads();
+    int bad = 0;
+    for (int base = 0; base < P.nz; base += W)
+        bad += finish_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez, base, step0 + nsteps);
+    if (bad) atomicAdd(&sh.bad, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->cur = cur ^ 1;
+        st->step = step0 + nsteps;
+        st->lag_valid = 1;
+        st->nonfinite = sh.bad;
+    }
+}
+
+template <int T, int CPT>
+__global__ __launch_bounds__(T) void k_batch1d(BatchArgs a)
+{
+    __shared__ Lds<T, CPT> sh;
+    const int i = a.order[blockIdx.x];
+    const BInst P = a.inst[i];
+    if (P.closure == LEC)
+        run_instance<LEC, T, CPT>(a, P, a.st + i, sh);
+    else
+        run_instance<WARMC, T, CPT>(a, P, a.st + i, sh);
+}
+
+struct Config {
+    int threads, cpt;
+};
+// (1024 threads with two nodes each would spill registers at the 128-VGPR
+// limit of 1024-thread workgroups)
+const Config CONFIGS[] = {{256, 1}, {256, 2}, {512, 1}, {512, 2}, {1024, 1}};
+constexpr int NCONFIG = sizeof(CONFIGS) / sizeof(CONFIGS[0]);
+
+void launch_config(int ci, const BatchArgs &a, int nblocks, hipStream_t s)
+{
+    switch (ci) {
+    case 0: hipLaunchKernelGGL((k_batch1d<256, 1>), dim3(nblocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_batch1d<256, 2>), dim3(nblocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_batch1d<512, 1>), dim3(nblocks), dim3(512), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_batch1d<512, 2>), dim3(nblocks), dim3(512), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_batch1d<1024, 1>), dim3(nblocks), dim3(1024), 0, s, a); break;
+    }
+}
+
+struct BLayout {
+    size_t inst, order, st, pop[2], ez, lag, snap_pop, snap_ez, snap_lag, snap_st, zeros, total;
+    size_t pop_elems, fld_elems, lag_elems;
+};
+
+bool inst_valid(const lbw_instance_desc &d, std::string *why)
+{
+    auto bad = [&](const char *m) { if (why) *why = m; return false; };
+    if (d.nz < 4) return bad("nz must be >= 4");
+    if (d.nz > (1 << 24)) return bad("nz must be <= 2^24");
+    if (d.closure != LBW_LEC && d.closure != LBW_WARMC) return bad("unknown closure");
+    if (!(d.dvel > 0)) return bad("dvel must be positive");
+    if (!(d.mu >= 0) || !std::isfinite(d.mu)) return bad("mu must be >= 0");
+    if (!(d.delta > 0) || !(d.dt > 0)) return bad("delta and dt must be positive");
+    if (d.bc != LBW_BC_OPEN && d.bc != LBW_BC_PERIODIC) return bad("unknown bc");
+    if (!std::isfinite(d.alpha)) return bad("alpha must be finite");
+    if (d.alpha != 0.0 && !(d.sigma_z > 0)) return bad("sigma_z must be positive");
+    return true;
+}
+
+int nscal1(int closure) { return closure == LBW_LEC ? 2 : 4; }
+size_t padded(int nz) { return ((size_t)nz + PAD - 1) / PAD * PAD; }
+
+BLayout make_blayout(const lbw_instance_desc *d, int n)
+{
+    BLayout L{};
+    size_t pe = 0, fe = 0, le = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t np = padded(d[i].nz);
+        pe += (size_t)nscal1(d[i].closure) * 3 * np;
+        fe += np;
+        if (d[i].closure == LBW_WARMC) le += NLAG1 * np;
+    }
+    L.pop_elems = pe;
+    L.fld_elems = fe;
+    L.lag_elems = le;
+    size_t off = 0;
+    L.inst = off; off += align_up(n * sizeof(BInst));
+    L.order = off; off += align_up(n * sizeof(int));
+    L.st = off; off += align_up(n * sizeof(BState));
+    L.pop[0] = off; off += align_up(pe * 8);
+    L.pop[1] = off; off += align_up(pe * 8);
+    L.ez = off; off += align_up(fe * 8);
+    L.lag = off; off += align_up(le * 8 + 8);
+    L.snap_pop = off; off += align_up(pe * 8);
+    L.snap_ez = off; off += align_up(fe * 8);
+    L.snap_lag = off; off += align_up(le * 8 + 8);
+    L.snap_st = off; off += align_up(n * sizeof(BState));
+    L.zeros = off; off += align_up(8 * 8);
+    L.total = off;
+    return L;
+}
+
+double lambda_rest1(double mu, double D) { return 0.5 * (D * mu + std::sqrt(D * D * mu * mu + 4.0)); }
+
+}  // namespace
+
+struct lbw_batch {
+    std::vector<lbw_instance_desc> d;
+    std::vector<BInst> inst;
+    std::vector<int> order;
+    BLayout L;
+    char *ws;
+    hipStream_t stream, capture_stream;
+    hipEvent_t ev[2];
+    bool ev_recorded;
+    int cfg;
+    bool initialized;
+    long step;
+    int cur;  // host mirror of every instance's buffer parity
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+    std::string err;
+};
+
+static lbw_status bfail(lbw_batch *b, lbw_status code, const std::string &m)
+{
+    if (b) b->err = m;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                     \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return bfail((b), LBW_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static BatchArgs batch_args(lbw_batch *b, int nsteps)
+{
+    BatchArgs a{};
+    a.inst = (const BInst *)(b->ws + b->L.inst);
+    a.order = (const int *)(b->ws + b->L.order);
+    a.pop0 = (double *)(b->ws + b->L.pop[0]);
+    a.pop1 = (double *)(b->ws + b->L.pop[1]);
+    a.ez = (double *)(b->ws + b->L.ez);
+    a.lag = (double *)(b->ws + b->L.lag);
+    a.st = (BState *)(b->ws + b->L.st);
+    a.nsteps = nsteps;
+    return a;
+}
+
+// One instance seen as a single 1D run by the initialisation and read-out
+// kernels shared with lbw_step: its planes are nzp nodes apart, so those
+// kernels run over ncell = nzp nodes (the padding nodes are never read by
+// the step).
+static StepArgs instance_args(lbw_batch *b, int i)
+{
+    const BInst &P = b->inst[i];
+    StepArgs a{};
+    a.nz = P.nz;
+    a.nx = 1;
+    a.ncell = P.nzp;
+    a.bcz = P.bc;
+    a.bcx = BC_OPEN;
+    a.delta = P.delta;
+    a.dt = P.dt;
+    a.inv2d = P.inv2d;
+    a.omega = P.omega;
+    a.lam = P.lam;
+    a.mu = P.mu;
+    a.a_lec = P.a_lec;
+    a.two_over_d = P.two_over_d;
+    a.dcode = P.dcode;
+    a.aref = (const double *)(b->ws + b->L.zeros);
+    a.drv = P.drv;
+    a.step = b->step;
+    a.src = (double *)(b->ws + b->L.pop[b->cur]) + P.pop;
+    a.dst = nullptr;
+    a.ez_in = (const double *)(b->ws + b->L.ez) + P.fld;
+    a.ez_out = (double *)(b->ws + b->L.ez) + P.fld;
+    return a;
+}
+
+extern "C" {
+
+size_t lbw_batch_workspace_bytes(const lbw_instance_desc *d, int n)
+{
+    if (!d || n < 1 || n > MAX_INST) return 0;
+    for (int i = 0; i < n; ++i)
+        if (!inst_valid(d[i], nullptr)) return 0;
+    return make_blayout(d, n).total;
+}
+
+lbw_status lbw_batch_create(const lbw_instance_desc *d, int n, void *ws, size_t ws_bytes, void *stream,
+                            lbw_batch **out)
+{
+    if (!out) return LBW_ERR_ARG;
+    *out = nullptr;
+    if (!d || n < 1 || n > MAX_INST) return LBW_ERR_ARG;
+    for (int i = 0; i < n; ++i) {
+        if (!inst_valid(d[i], nullptr)) return LBW_ERR_ARG;
+        if (!(d[i].tau_tilde > 0.5)) return LBW_ERR_UNSTABLE;
+        if (d[i].dt > d[i].delta * (1.0 + 1e-12)) return LBW_ERR_UNSTABLE;
+    }
+    const BLayout L = make_blayout(d, n);
+    if (!ws || ws_bytes < L.total || ((uintptr_t)ws % ALIGN) != 0) return LBW_ERR_WORKSPACE;
+    lbw_batch *b = new lbw_batch();
+    b->d.assign(d, d + n);
+    b->L = L;
+    b->ws = (char *)ws;
+    b->stream = (hipStream_t)stream;
+    b->capture_stream = nullptr;
+    b->ev_recorded = false;
+    b->cfg = 4;  // 1024 threads, one node per thread
+    b->initialized = false;
+    b->step = 0;
+    b->cur = 0;
+    size_t pe = 0, fe = 0, le = 0;
+    for (int i = 0; i < n; ++i) {
+        const lbw_instance_desc &q = d[i];
+        BInst P{};
+        P.nz = q.nz;
+        P.nzp = (int)padded(q.nz);
+        P.closure = q.closure;
+        P.bc = q.bc;
+        P.dcode = q.dvel == 1.0 ? 1 : (q.dvel == 3.0 ? 3 : 0);
+        P.K = nscal1(q.closure);
+        P.pop = pe;
+        P.fld = fe;
+        P.lag = le;
+        pe += (size_t)P.K * 3 * P.nzp;
+        fe += P.nzp;
+        if (q.closure == LBW_WARMC) le += NLAG1 * (size_t)P.nzp;
+        P.delta = q.delta;
+        P.dt = q.dt;
+        P.inv2d = 1.0 / (2.0 * q.delta);
+        P.omega = 1.0 / q.tau_tilde;
+        P.lam = q.delta / q.dt;
+        P.mu = q.mu;
+        P.a_lec = (1.0 + 0.5 * q.dvel) * q.mu;
+        P.two_over_d = 2.0 / q.dvel;
+        P.dvel = q.dvel;
+        Driver v{};
+        v.alpha = q.alpha;
+        v.sigma_z = q.sigma_z;
+        v.z0 = q.z0;
+        v.inv2sz2 = q.sigma_z > 0 ? 1.0 / (2.0 * q.sigma_z * q.sigma_z) : 0.0;
+        v.nslices = 0;
+        v.slice_w = nullptr;
+        P.drv = v;
+        b->inst.push_back(P);
+    }
+    b->order.resize(n);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    // longest first (ties by index): the longest runs start first
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int x, int y) { return d[x].nz > d[y].nz; });
+    lbw_status rc = LBW_OK;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && rc == LBW_OK) rc = bfail(b, LBW_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    chk(hipEventCreate(&b->ev[0]), "hipEventCreate");
+    chk(hipEventCreate(&b->ev[1]), "hipEventCreate");
+    chk(hipMemcpyAsync(b->ws + L.inst, b->inst.data(), n * sizeof(BInst), hipMemcpyHostToDevice, b->stream),
+        "hipMemcpyAsync");
+    chk(hipMemcpyAsync(b->ws + L.order, b->order.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream),
+        "hipMemcpyAsync");
+    chk(hipMemsetAsync(b->ws + L.zeros, 0, 64, b->stream), "hipMemsetAsync");
+    chk(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    if (rc != LBW_OK) {
+        lbw_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBW_OK;
+}
+
+void lbw_batch_destroy(lbw_batch *b)
+{
+    if (!b) return;
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : b->graph_defs) (void)hipGraphDestroy(g);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    (void)hipEventDestroy(b->ev[0]);
+    (void)hipEventDestroy(b->ev[1]);
+    delete b;
+}
+
+const char *lbw_batch_last_error(const lbw_batch *b) { return b ? b->err.c_str() : "NULL batch"; }
+
+long lbw_batch_step_count(const lbw_batch *b) { return b ? b->step : -1; }
+
+lbw_status lbw_batch_init(lbw_batch *b, const double *n_init)
+{
+    if (!b) return LBW_ERR_ARG;
+    const int n = (int)b->inst.size();
+    b->initialized = false;
+    b->step = 0;
+    b->cur = 0;
+    std::vector<BState> st(n);
+    for (auto &x : st) x = BState{0, 0, 0, 0, {0, 0, 0}};
+    BHIPCHK(b, hipMemcpyAsync(b->ws + b->L.st, st.data(), n * sizeof(BState), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemsetAsync(b->ws + b->L.ez, 0, b->L.fld_elems * 8, b->stream));
+    BHIPCHK(b, hipMemsetAsync(b->ws + b->L.lag, 0, b->L.lag_elems * 8 + 8, b->stream));
+    size_t off = 0;
+    std::vector<double> A;
+    for (int i = 0; i < n; ++i) {
+        const BInst &P = b->inst[i];
+        const size_t nz = P.nz, np = P.nzp;
+        const int K = P.K;
+        // moments A [K][nzp] and a zero velocity [2][nzp], staged in the
+        // instance's second population buffer (K x 3 x nzp >= (K + 2) x nzp)
+        A.assign((size_t)(K + 2) * np, 0.0);
+        for (size_t c = 0; c < np; ++c) {
+            double dens = 1.0;
+            if (c < nz && n_init) {
+                dens = n_init[off + c];
+                if (!(dens > 0.0) || !std::isfinite(dens))
+                    return bfail(b, LBW_ERR_NONFINITE, "initial density must be positive and finite");
+            }
+            A[c] = dens;
+            if (P.closure == LBW_WARMC) {
+                // rest state: n lambda_0 (eq. traces3) and lambda_0 theta^zz, theta^zz = n mu
+                const double l0 = lambda_rest1(P.mu, P.dvel);
+                A[1 * np + c] = dens * l0;
+                A[3 * np + c] = l0 * dens * P.mu;
+            }
+        }
+        off += nz;
+        double *stage = (double *)(b->ws + b->L.pop[1]) + P.pop;
+        BHIPCHK(b, hipMemcpyAsync(stage, A.data(), A.size() * 8, hipMemcpyHostToDevice, b->stream));
+        StepArgs a = instance_args(b, i);
+        const double *uz = stage + (size_t)K * np, *ux = uz + np;
+        const int nb = (int)((np + 255) / 256);
+        double *dst = (double *)(b->ws + b->L.pop[0]) + P.pop;
+        if (P.closure == LBW_LEC)
+            hipLaunchKernelGGL((k_init_pops<1, LEC, double>), dim3(nb), dim3(256), 0, b->stream, (void *)dst,
+                               (const double *)stage, uz, ux, a.aref, (int)np, P.lam);
+        else
+            hipLaunchKernelGGL((k_init_pops<1, WARMC, double>), dim3(nb), dim3(256), 0, b->stream,
+                               (void *)dst, (const double *)stage, uz, ux, a.aref, (int)np, P.lam);
+        BHIPCHK(b, hipGetLastError());
+        if (P.drv.alpha != 0.0) {
+            // causal field of the bunch (as lbw_init_driver with init_fields)
+            StepArgs f = a;
+            f.ncell = P.nz;
+            double *ez = (double *)(b->ws + b->L.ez) + P.fld;
+            hipLaunchKernelGGL(k_init_fields<1>, dim3((P.nz + 255) / 256), dim3(256), 0, b->stream, f, ez,
+                               (double *)nullptr, (double *)nullptr);
+            BHIPCHK(b, hipGetLastError());
+        }
+        BHIPCHK(b, hipStreamSynchronize(b->stream));  // the host staging vector is reused
+    }
+    b->initialized = true;
+    return LBW_OK;
+}
+
+static lbw_status launch_step(lbw_batch *b, int nsteps, int use_graph)
+{
+    const BatchArgs a = batch_args(b, nsteps);
+    const int nblocks = (int)b->inst.size();
+    if (!use_graph) {
+        launch_config(b->cfg, a, nblocks, b->stream);
+        BHIPCHK(b, hipGetLastError());
+        return LBW_OK;
+    }
+    const auto key = std::make_pair(nsteps, b->cfg);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        // capture on a private stream: the caller's may be the null stream
+        if (!b->capture_stream) BHIPCHK(b, hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        BHIPCHK(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+        launch_config(b->cfg, a, nblocks, b->capture_stream);
+        const hipError_t le = hipGetLastError();
+        const hipError_t ce = hipStreamEndCapture(b->capture_stream, &g);
+        BHIPCHK(b, le);
+        BHIPCHK(b, ce);
+        b->graph_defs.push_back(g);
+        hipGraphExec_t ex = nullptr;
+        BHIPCHK(b, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        it = b->graphs.emplace(key, ex).first;
+    }
+    BHIPCHK(b, hipGraphLaunch(it->second, b->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_batch_step(lbw_batch *b, int nsteps, int use_graph)
+{
+    if (!b) return LBW_ERR_ARG;
+    if (!b->initialized) return bfail(b, LBW_ERR_STATE, "lbw_batch_init first");
+    if (nsteps < 0) return bfail(b, LBW_ERR_ARG, "nsteps must be >= 0");
+    if (nsteps == 0) return LBW_OK;
+    BHIPCHK(b, hipEventRecord(b->ev[0], b->stream));
+    lbw_status rc = launch_step(b, nsteps, use_graph);
+    if (rc != LBW_OK) return rc;
+    BHIPCHK(b, hipEventRecord(b->ev[1], b->stream));
+    b->ev_recorded = true;
+    b->step += nsteps;
+    b->cur ^= (nsteps + 1) & 1;
+    return LBW_OK;
+}
+
+lbw_status lbw_batch_get_timing(lbw_batch *b, double *ms)
+{
+    if (!b || !ms) return LBW_ERR_ARG;
+    if (!b->ev_recorded) return bfail(b, LBW_ERR_STATE, "no lbw_batch_step yet");
+    BHIPCHK(b, hipEventSynchronize(b->ev[1]));
+    float f = 0.0f;
+    BHIPCHK(b, hipEventElapsedTime(&f, b->ev[0], b->ev[1]));
+    *ms = f;
+    return LBW_OK;
+}
+
+lbw_status lbw_batch_set_config(lbw_batch *b, int threads, int cpt)
+{
+    if (!b) return LBW_ERR_ARG;
+    for (int i = 0; i < NCONFIG; ++i)
+        if (CONFIGS[i].threads == threads && CONFIGS[i].cpt == cpt) {
+            b->cfg = i;
+            return LBW_OK;
+        }
+    return bfail(b, LBW_ERR_ARG, "configuration must be 256 or 512 threads with 1 or 2 nodes each, or 1024 threads with 1");
+}
+
+lbw_status lbw_batch_get_config(const lbw_batch *b, int *threads, int *cpt)
+{
+    if (!b || !threads || !cpt) return LBW_ERR_ARG;
+    *threads = CONFIGS[b->cfg].threads;
+    *cpt = CONFIGS[b->cfg].cpt;
+    return LBW_OK;
+}
+
+static lbw_status snapshot(lbw_batch *b, bool save)
+{
+    const BLayout &L = b->L;
+    // the canonical state: the current population buffer, E_z, lagged
+    // values and the per-instance state records
+    const size_t pairs[4][3] = {{L.pop[b->cur], L.snap_pop, L.pop_elems * 8},
+                                {L.ez, L.snap_ez, L.fld_elems * 8},
+                                {L.lag, L.snap_lag, L.lag_elems * 8},
+                                {L.st, L.snap_st, b->inst.size() * sizeof(BState)}};
+    for (auto &p : pairs) {
+        if (p[2] == 0) continue;
+        char *live = b->ws + p[0], *copy = b->ws + p[1];
+        BHIPCHK(b, hipMemcpyAsync(save ? copy : live, save ? live : copy, p[2], hipMemcpyDeviceToDevice, b->stream));
+    }
+    return LBW_OK;
+}
+
+lbw_status lbw_batch_autotune(lbw_batch *b, int probe_steps, int *threads, int *cpt)
+{
+    if (!b) return LBW_ERR_ARG;
+    if (!b->initialized) return bfail(b, LBW_ERR_STATE, "lbw_batch_init first");
+    if (probe_steps < 1) return bfail(b, LBW_ERR_ARG, "probe_steps must be >= 1");
+    const long step0 = b->step;
+    const int cur0 = b->cur;
+    lbw_status rc = snapshot(b, true);
+    if (rc != LBW_OK) return rc;
+    double best = 1e300;
+    int best_i = b->cfg;
+    for (int i = 0; i < NCONFIG; ++i) {
+        b->cfg = i;
+        // one untimed launch (first use of this kernel), then the timed one
+        for (int rep = 0; rep < 2; ++rep) {
+            rc = snapshot(b, false);
+            b->step = step0;
+            b->cur = cur0;
+            if (rc == LBW_OK) rc = lbw_batch_step(b, probe_steps, 0);
+            if (rc != LBW_OK) break;
+        }
+        double ms = 0.0;
+        if (rc == LBW_OK) rc = lbw_batch_get_timing(b, &ms);
+        if (rc != LBW_OK) break;
+        if (ms < best) {
+            best = ms;
+            best_i = i;
+        }
+    }
+    b->step = step0;
+    b->cur = cur0;
+    lbw_status rc2 = snapshot(b, false);
+    if (rc == LBW_OK) rc = rc2;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->cfg = best_i;
+    if (threads) *threads = CONFIGS[best_i].threads;
+    if (cpt) *cpt = CONFIGS[best_i].cpt;
+    return rc;
+}
+
+lbw_status lbw_batch_read(lbw_batch *b, int i, int which, double *host_out, size_t count)
+{
+    if (!b || !host_out) return bfail(b, LBW_ERR_ARG, "NULL argument");
+    if (!b->initialized) return bfail(b, LBW_ERR_STATE, "lbw_batch_init first");
+    if (i < 0 || i >= (int)b->inst.size()) return bfail(b, LBW_ERR_ARG, "instance index out of range");
+    const BInst &P = b->inst[i];
+    if (count != (size_t)P.nz) return bfail(b, LBW_ERR_ARG, "count must be the instance's nz");
+    if (!((which >= 0 && which < LBW_NMOMENTS) || which == LBW_BATCH_EZ))
+        return bfail(b, LBW_ERR_ARG, "unknown observable");
+    StepArgs a = instance_args(b, i);
+    // output staged in the instance's free population buffer
+    double *out = (double *)(b->ws + b->L.pop[b->cur ^ 1]) + P.pop;
+    const int nb = (P.nzp + 255) / 256;
+    if (which == LBW_BATCH_EZ)
+        hipLaunchKernelGGL(k_read_field<1>, dim3(nb), dim3(256), 0, b->stream, a, 0, 1, out);
+    else if (P.closure == LBW_LEC)
+        hipLaunchKernelGGL((k_read_moment<1, LEC, double>), dim3(nb), dim3(256), 0, b->stream, a, which, out);
+    else
+        hipLaunchKernelGGL((k_read_moment<1, WARMC, double>), dim3(nb), dim3(256), 0, b->stream, a, which, out);
+    BHIPCHK(b, hipGetLastError());
+    BHIPCHK(b, hipMemcpyAsync(host_out, out, count * 8, hipMemcpyDeviceToHost, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_batch_nonfinite(lbw_batch *b, int *counts)
+{
+    if (!b || !counts) return bfail(b, LBW_ERR_ARG, "NULL argument");
+    const int n = (int)b->inst.size();
+    std::vector<BState> st(n);
+    BHIPCHK(b, hipMemcpyAsync(st.data(), b->ws + b->L.st, n * sizeof(BState), hipMemcpyDeviceToHost, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int i = 0; i < n; ++i) counts[i] = st[i].nonfinite;
+    return LBW_OK;
+}
+
+}  // extern "C"

@@ -497,7 +497,7 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
 }
 
 // Pass 2 (2D): B^{n-1/2} = (B^{n-3/2} - dt/2 curl E^{n-1}) - dt/2 curl E^{n-1}.
-__global__ void k_finish_b2d(StepArgs a)
+static __global__ void k_finish_b2d(StepArgs a)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.ncell) return;
@@ -512,7 +512,7 @@ __global__ void k_finish_b2d(StepArgs a)
 }
 
 // Pass 3 (2D): E^n = E^{n-1} + dt (curl B^{n-1/2} - J^n - J_b^{n-1/2}).
-__global__ void k_finish_e2d(StepArgs a, const double *jz, const double *jx)
+static __global__ void k_finish_e2d(StepArgs a, const double *jz, const double *jx)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.ncell) return;
@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, double *part)
         for (int d = 0; d < NDIAG; ++d) part[(size_t)d * gridDim.x + blockIdx.x] = red[d][0];
 }
 
-__global__ __launch_bounds__(256) void k_diag_final(const double *part, int nblocks, double *out)
+static __global__ __launch_bounds__(256) void k_diag_final(const double *part, int nblocks, double *out)
 {
     __shared__ double red[NDIAG][256];
     double v[NDIAG] = {0, 0, 0, 0, 0, 0};

@@ -76,3 +76,20 @@ def initial_density(w):
     if w.get("noise", 0.0) > 0.0:
         return density_noise(shape, w["noise"], w["seed"])
     return np.ones(shape)
+
+
+# The batched 1D scan: 256 instances of batch_scan(seed 0), delta = lambda_p/128,
+# D = 1, open boundaries, 4096 steps.
+BATCH_SCAN = dict(n_inst=256, seed=0, delta=LAMBDA_P / 128, dvel=1.0, steps=4096)
+
+
+def batch_instances(n_inst=None, seed=None):
+    """Instance descriptors of the batched scan (keys of the batch binding)."""
+    n_inst = BATCH_SCAN["n_inst"] if n_inst is None else n_inst
+    seed = BATCH_SCAN["seed"] if seed is None else seed
+    delta = BATCH_SCAN["delta"]
+    out = []
+    for d in batch_scan(n_inst, seed):
+        out.append(dict(d, delta=delta, dt=0.1 * delta, tau_tilde=0.52, dvel=BATCH_SCAN["dvel"],
+                        bc="open", z0=6.0 * d["sigma_z"]))
+    return out

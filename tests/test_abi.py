@@ -82,3 +82,43 @@ def test_create_validation(lib):
     assert _create(lib, _grid(), ws=256 * 1024 + 8)[0] == -2      # misaligned workspace
     assert _create(lib, _grid(), nbytes=1024)[0] == -2            # too small
     assert _create(lib, _grid(nz=1))[0] == -1
+
+
+def _inst(**kw):
+    d = dict(nz=1000, closure=0, dvel=1.0, mu=1e-3, delta=0.05, dt=0.005, tau_tilde=0.52, bc=0,
+             alpha=0.5, sigma_z=0.5, z0=3.0)
+    d.update(kw)
+    return _lib.InstanceDesc(**d)
+
+
+def _insts(*ds):
+    return (_lib.InstanceDesc * len(ds))(*ds)
+
+
+def test_batch_workspace_bytes(lib):
+    one = _insts(_inst())
+    n1 = lib.lbw_batch_workspace_bytes(one, 1)
+    # two LEC population buffers (2 x 3 planes of 1024 padded nodes) and E_z at least
+    assert n1 >= 2 * 6 * 1024 * 8 + 1024 * 8
+    two = _insts(_inst(), _inst(closure=1, nz=3000))
+    assert lib.lbw_batch_workspace_bytes(two, 2) >= n1 + 2 * 12 * 3008 * 8
+    assert lib.lbw_batch_workspace_bytes(_insts(_inst(nz=3)), 1) == 0
+    assert lib.lbw_batch_workspace_bytes(_insts(_inst(closure=4)), 1) == 0
+    assert lib.lbw_batch_workspace_bytes(_insts(_inst(alpha=1.0, sigma_z=0.0)), 1) == 0
+    assert lib.lbw_batch_workspace_bytes(one, 0) == 0
+
+
+def test_batch_create_validation(lib):
+    def create(arr, n, ws=256 * 1024, nbytes=None):
+        h = ctypes.c_void_p()
+        if nbytes is None:
+            nbytes = lib.lbw_batch_workspace_bytes(arr, n)
+        rc = lib.lbw_batch_create(arr, n, ctypes.c_void_p(ws), nbytes, None, ctypes.byref(h))
+        return rc
+    # every check below returns before any device call
+    assert create(_insts(_inst(tau_tilde=0.5)), 1) == -4
+    assert create(_insts(_inst(dt=0.06)), 1) == -4                 # dt > delta
+    assert create(_insts(_inst(nz=2)), 1, nbytes=1 << 20) == -1
+    assert create(_insts(_inst()), 1, ws=256 * 1024 + 8) == -2      # misaligned
+    assert create(_insts(_inst()), 1, nbytes=64) == -2              # too small
+    assert create(_insts(_inst()), 0, nbytes=1 << 20) == -1
