@@ -183,6 +183,46 @@ lbw_status lbw_save_state(lbw_sim *sim, void *host, size_t bytes);
 lbw_status lbw_load_state(lbw_sim *sim, const void *host, size_t bytes);
 
 /* ---------------------------------------------------------------------------
+ * Device-side checkpoints of the canonical state (f^n, E^n, B^{n-1/2} and the
+ * warm closure's lagged values) for checkpoint-and-recompute. The buffer is
+ * caller-owned device memory, 256-byte aligned, of lbw_state_device_bytes();
+ * layout: the populations (storage type), then E_z, E_x, B_y (FP64), then the
+ * lagged values, each part starting on a 256-byte boundary. Both calls are
+ * asynchronous on the simulation's stream. lbw_load_state_device restores a
+ * state saved from a simulation with the same descriptor and plasma (it
+ * keeps the current mu, storage reference and driver) and sets the step
+ * counter to step. */
+size_t lbw_state_device_bytes(const lbw_sim *sim);
+lbw_status lbw_save_state_device(lbw_sim *sim, void *device_dst);
+lbw_status lbw_load_state_device(lbw_sim *sim, const void *device_src, long step);
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint of the 2D local-equilibrium step (Sec. 2.2, Sec. 3.1,
+ * Sec. 5): the transposed Jacobian of one step of lbw_step, and the
+ * derivatives of the driver's slice weights (per-slice current profile) in
+ * the bunch current and in the initial fields. 2D, LBW_LEC, any storage
+ * (the adjoint itself is FP64); LBW_ERR_UNSUPPORTED otherwise, LBW_ERR_STATE
+ * when the driver has no slices.
+ *
+ * adj (device, FP64, caller-owned) holds the adjoint of a canonical state:
+ * K*Q population planes in the population order, then E_z, E_x, B_y, each
+ * nx*nz values; lbw_adjoint_bytes() bytes. scratch: lbw_adjoint_workspace_bytes()
+ * bytes of device memory, 256-byte aligned. grad: nslices FP64 values on the
+ * device, accumulated into (the caller zeroes it).
+ *
+ * lbw_adjoint_step: given the saved states at steps n and n+1
+ * (lbw_save_state_device) and the adjoint of state n+1 in adj, overwrite adj
+ * with the adjoint of state n and add the step's slice derivatives to grad.
+ * lbw_adjoint_init_fields: with adj the adjoint of state 0, add the slice
+ * derivatives of the initial fields (lbw_init_driver with init_fields).
+ * Both are asynchronous on the simulation's stream. */
+size_t lbw_adjoint_bytes(const lbw_sim *sim);
+size_t lbw_adjoint_workspace_bytes(const lbw_sim *sim);
+lbw_status lbw_adjoint_step(lbw_sim *sim, const void *state_n, const void *state_n1, long n, double *adj,
+                            double *grad, void *scratch);
+lbw_status lbw_adjoint_init_fields(lbw_sim *sim, const double *adj, double *grad, void *scratch);
+
+/* ---------------------------------------------------------------------------
  * Batched 1D parameter scans (one launch for many independent 1D runs).
  *
  * A batch holds ninst independent 1D simulations ("instances") of their own

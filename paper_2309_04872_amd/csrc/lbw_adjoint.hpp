@@ -1,0 +1,416 @@
+// lbw_adjoint.hpp -- discrete adjoint of one 2D local-equilibrium step
+// (transposed Jacobian of the map (f^n, E^n, B^{n-1/2}) -> (f^{n+1}, E^{n+1},
+// B^{n+1/2}) of lbw_step) and the derivatives of the driver terms with
+// respect to the slice weights. All adjoint arithmetic is FP64.
+//
+// Forward map of one step (Sec. 2.2, Sec. 3.1, Sec. 5; the fused kernel and
+// the finish kernels compute exactly this):
+//   S1 A_k = sum_q f_kq                       S2 (u, phi) = recovery(A)
+//   S3 Bh = B - dt/2 curlE(E);  node fields En_z, En_x (2-point), Bn_y (4-point of Bh)
+//   S5 F_z = -mu d_z phi - n (En_z + u_x Bn_y), F_x = -mu d_x phi - n (En_x - u_z Bn_y)
+//   S6 f*_kq = (1 - omega) f_kq + omega w_q A_k (1 + P_q(u)) + dt w_q F_k
+//   S7 f'_kq(c) = f*_kq(fix(c - e_q))         S8 m' = n' u' = recovery(A')
+//   S9 B' = Bh - dt/2 curlE(E);  E'_x = E_x + dt (curlB_x(B') + (m'_x(c) + m'_x(c + x))/2)
+//      E'_z = E_z + dt (curlB_z(B') + (m'_z(c) + m'_z(c + z))/2 + n_b(w))
+// The reverse step runs S9..S1 backwards. Every read of the forward goes
+// through a boundary rule (copy ghost or wrap); its transpose gathers, for a
+// target slot, from every slot whose read lands there (pre1 below), so the
+// reverse step is a pure gather: deterministic, no atomics.
+#pragma once
+
+#include "lbw_device.hpp"
+
+namespace lbw {
+
+struct AdjArgs {
+    const void *fn, *fn1;                 // populations of the states at steps n and n+1
+    const double *ez, *ex, *by;           // E^n, B^{n-1/2} (Yee arrays)
+    double *lf, *lez, *lex, *lby;         // adjoint of the state, updated in place
+    double *s_byt, *s_fs, *s_fz, *s_fx;   // scratch: adjoint of B', of f*, of F
+    double *s_enz, *s_enx, *s_bny, *s_bht, *s_col;
+    const double *aref;
+    double *grad;                         // d loss / d slice weight, accumulated
+    int nz, nx, ncell, bcz, bcx;
+    double delta, dt, omega, lam, mu, a_lec, two_over_d, dvel;
+    int dcode;
+    long step;                            // n
+    Driver drv;
+};
+
+// Positions c in [0, n) whose read of index c + d lands on y under the node
+// (copy ghost) or staggered rule, or the periodic wrap; at most 3.
+__device__ __forceinline__ int pre1(int y, int d, int n, int bc, bool stag, int *out)
+{
+    if (bc == BC_PERIODIC) {
+        int c = (y - d) % n;
+        out[0] = c < 0 ? c + n : c;
+        return 1;
+    }
+    const int cand[4] = {y - d, 0, n - 2, n - 1};
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = cand[k];
+        if (c < 0 || c >= n) continue;
+        bool dup = false;
+        for (int m = 0; m < cnt; ++m) dup |= out[m] == c;
+        if (dup) continue;
+        const int v = stag ? fix_stag(c + d, n, bc) : fix_node(c + d, n, bc);
+        if (v == y) out[cnt++] = c;
+    }
+    return cnt;
+}
+
+// Sum over every slot c of X[c] whose read at (c_x + dx, c_z + dz) lands on
+// (jy, iy) under the given rules (sx / sz: staggered along x / z).
+__device__ __forceinline__ double gather2(const double *X, int jy, int iy, int dx, int dz, bool sx, bool sz,
+                                          int nx, int nz, int bcx, int bcz)
+{
+    int cx[3], cz[3];
+    const int nxc = pre1(jy, dx, nx, bcx, sx, cx);
+    const int nzc = pre1(iy, dz, nz, bcz, sz, cz);
+    double acc = 0.0;
+    for (int a = 0; a < nxc; ++a)
+        for (int b = 0; b < nzc; ++b) acc += X[(size_t)cx[a] * nz + cz[b]];
+    return acc;
+}
+
+// Forward recovery of one node with the quantities its derivative needs.
+// u = kappa a_1 with kappa = 1 / (n gamma h), h = 1 + s, s = a (n/gamma)^{2/D},
+// t = (2/D) s; the root p of p h(p, n) = P = |a_1|/n has
+// dp/dP = 1 / (h - t p^2/gamma^2), dp/dn = -(p t / n) dp/dP (implicit function
+// of the fixed-point equation of Sec. 3.1).
+struct LecJ {
+    double n, az, ax, uz, ux, g, p, h, t, kappa, phi, dpdP, dpdn, P;
+};
+
+__device__ __forceinline__ void lec_jac(double n, double az, double ax, const AdjArgs &a, LecJ &J)
+{
+    LecRec r;
+    lec_recover(n, az, ax, a.a_lec, a.dcode, a.two_over_d, r);
+    J.n = n;
+    J.az = az;
+    J.ax = ax;
+    J.uz = r.uz;
+    J.ux = r.ux;
+    J.g = r.gamma;
+    J.phi = r.phi;
+    J.p = r.gamma * hypot(r.uz, r.ux);
+    const double x = n / r.gamma;
+    const double s = a.a_lec * (a.dcode == 3 ? cbrt(x * x) : (a.dcode == 1 ? x * x : pow(x, a.two_over_d)));
+    J.h = 1.0 + s;
+    J.t = a.two_over_d * s;
+    J.kappa = 1.0 / (n * r.gamma * J.h);
+    const double Dd = J.h - J.t * J.p * J.p / (J.g * J.g);
+    J.dpdP = 1.0 / Dd;
+    J.dpdn = -(J.p * J.t / n) * J.dpdP;
+    J.P = (ax == 0.0 ? fabs(az) : hypot(az, ax)) / n;
+}
+
+// Reverse of the recovery: adjoints (uzb, uxb) of u, phib of phi and nb of n
+// itself -> adjoints of (A_0, A_1z, A_1x). The p-derivatives of kappa and phi
+// carry a factor p, which cancels the 1/|a_1| of d|a_1|, so nothing divides
+// by |a_1| (cells at rest have a_1 = 0).
+__device__ __forceinline__ void lec_recover_adj(const LecJ &J, double uzb, double uxb, double phib, double nb,
+                                                double e_phi, double *Ab)
+{
+    const double g2 = J.g * J.g;
+    const double kb = uzb * J.az + uxb * J.ax;
+    const double kp = -J.kappa * (1.0 - J.t / J.h) / g2;  // (d kappa / d p) / p
+    const double kn = -(J.kappa / J.n) * (1.0 + J.t / J.h);
+    const double pp = -e_phi * J.phi / g2;                 // (d phi / d p) / p
+    const double pn = e_phi * J.phi / J.n;
+    const double qv = kb * kp + phib * pp;                 // adjoint of p, divided by p
+    nb += kb * kn + phib * pn;
+    nb += qv * J.p * J.dpdn;
+    nb -= qv * J.p * J.dpdP * J.P / J.n;
+    const double c1 = qv * J.dpdP / (J.n * J.n * J.h);
+    Ab[0] = nb;
+    Ab[1] = J.kappa * uzb + c1 * J.az;
+    Ab[2] = J.kappa * uxb + c1 * J.ax;
+}
+
+template <class ST>
+__device__ __forceinline__ void moments3(const void *f, const AdjArgs &a, size_t c, double *A)
+{
+    using L = Lattice<2>;
+    const ST *src = (const ST *)f;
+    const size_t nc = (size_t)a.ncell;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) acc += (double)Store<ST>::ld(src + (size_t)(k * L::Q + q) * nc, (int)c);
+        A[k] = a.aref[k] + acc;
+    }
+}
+
+// (a) Reverse of S9 and S8 at every slot/node y: adjoint of B', the currents'
+// adjoint m'b, through the recovery at n+1 into the adjoint of f'.
+template <class ST>
+__global__ void k_adj_maxwell(AdjArgs a)
+{
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.ncell) return;
+    const int iy = y % a.nz, jy = y / a.nz;
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    const double dt = a.dt, id = 1.0 / a.delta;
+    // B'(slot y) is read by curlB_z of E'_z at (j, i) and (j - 1, i), by curlB_x
+    // of E'_x at (j, i) and (j, i - 1)
+    double byt = a.lby[y];
+    byt += dt * id * (gather2(a.lez, jy, iy, 0, 0, true, true, nx, nz, bx, bz) -
+                      gather2(a.lez, jy, iy, -1, 0, true, true, nx, nz, bx, bz));
+    byt -= dt * id * (gather2(a.lex, jy, iy, 0, 0, true, true, nx, nz, bx, bz) -
+                      gather2(a.lex, jy, iy, 0, -1, true, true, nx, nz, bx, bz));
+    a.s_byt[y] = byt;
+    // m'_z(node y) enters E'_z at (j, i) and at (j, i - 1) (edge averages)
+    const double mzb = 0.5 * dt * (gather2(a.lez, jy, iy, 0, 0, false, false, nx, nz, bx, bz) +
+                                   gather2(a.lez, jy, iy, 0, 1, false, false, nx, nz, bx, bz));
+    const double mxb = 0.5 * dt * (gather2(a.lex, jy, iy, 0, 0, false, false, nx, nz, bx, bz) +
+                                   gather2(a.lex, jy, iy, 1, 0, false, false, nx, nz, bx, bz));
+    double A[3];
+    moments3<ST>(a.fn1, a, y, A);
+    LecJ J;
+    lec_jac(A[0], A[1], A[2], a, J);
+    // m = n u: adjoint of u is n m_b, n gets m_b . u
+    double Ab[3];
+    lec_recover_adj(J, A[0] * mzb, A[0] * mxb, 0.0, mzb * J.uz + mxb * J.ux, 1.0 + a.two_over_d, Ab);
+    const size_t nc = (size_t)a.ncell;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) a.lf[(size_t)(k * 9 + q) * nc + y] += Ab[k];
+}
+
+// (b) Reverse of S7 (streaming): adjoint of f* gathered from the nodes that
+// pulled from y; adjoint of the forcing F_k = dt sum_q w_q fs_b.
+__global__ void k_adj_stream(AdjArgs a)
+{
+    using L = Lattice<2>;
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.ncell) return;
+    const int iy = y % a.nz, jy = y / a.nz;
+    const size_t nc = (size_t)a.ncell;
+    double Fb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        int cx[3], cz[3];
+        const int nxc = pre1(jy, -L::ex(q), a.nx, a.bcx, false, cx);
+        const int nzc = pre1(iy, -L::ez(q), a.nz, a.bcz, false, cz);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double *lfq = a.lf + (size_t)(k * 9 + q) * nc;
+            double acc = 0.0;
+            for (int u = 0; u < nxc; ++u)
+                for (int v = 0; v < nzc; ++v) acc += lfq[(size_t)cx[u] * a.nz + cz[v]];
+            a.s_fs[(size_t)(k * 9 + q) * nc + y] = acc;
+            Fb[k] += L::w(q) * acc;
+        }
+    }
+    a.s_fz[y] = a.dt * Fb[1];
+    a.s_fx[y] = a.dt * Fb[2];
+}
+
+// Forward node fields at node (j, i) from E^n and B^{n-1/2} (S3).
+struct NodeF {
+    double ez, ex, by;
+};
+
+__device__ __forceinline__ double curl_e_at(const AdjArgs &a, int j, int i)
+{
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    auto EZ = [&](int jj, int ii) { return a.ez[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    auto EX = [&](int jj, int ii) { return a.ex[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
+    return ((EX(j, i + 1) - EX(j, i)) - (EZ(j + 1, i) - EZ(j, i))) / a.delta;
+}
+
+__device__ __forceinline__ NodeF node_fields_at(const AdjArgs &a, int j, int i)
+{
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    auto EZ = [&](int jj, int ii) { return a.ez[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    auto EX = [&](int jj, int ii) { return a.ex[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
+    auto BH = [&](int jj, int ii) {
+        const int js = fix_stag(jj, nx, bx), is = fix_stag(ii, nz, bz);
+        return a.by[(size_t)js * nz + is] - 0.5 * a.dt * curl_e_at(a, js, is);
+    };
+    NodeF f;
+    f.ez = 0.5 * (EZ(j, i - 1) + EZ(j, i));
+    f.ex = 0.5 * (EX(j - 1, i) + EX(j, i));
+    f.by = 0.25 * (BH(j, i) + BH(j, i - 1) + BH(j - 1, i) + BH(j - 1, i - 1));
+    return f;
+}
+
+// (c) Reverse of S6, S5, S2, S1 at node y: collision, forcing (the gradient
+// of phi gathers the forcing adjoint of the neighbours), recovery; writes
+// the adjoint of f^n and the node-field adjoints.
+template <class ST>
+__global__ void k_adj_collide(AdjArgs a)
+{
+    using L = Lattice<2>;
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.ncell) return;
+    const int iy = y % a.nz, jy = y / a.nz;
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    const size_t nc = (size_t)a.ncell;
+    double A[3];
+    moments3<ST>(a.fn, a, y, A);
+    LecJ J;
+    lec_jac(A[0], A[1], A[2], a, J);
+    const NodeF nf = node_fields_at(a, jy, iy);
+    const double uz = J.uz, ux = J.ux, n = A[0];
+    const double om = a.omega, lam = a.lam;
+    const double c1 = 3.0 / lam, c2 = 9.0 / (lam * lam), c3 = 3.0 / (lam * lam);
+    // collision adjoint
+    double Ab[3], uzb = 0.0, uxb = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double sa = 0.0, sz = 0.0, sx = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const double fb = a.s_fs[(size_t)(k * 9 + q) * nc + y];
+            const double ez = L::ez(q), ex = L::ex(q);
+            const double eu = uz * ez + ux * ex;
+            const double P = c1 * eu + 0.5 * c2 * eu * eu - 0.5 * c3 * (uz * uz + ux * ux);
+            const double wf = L::w(q) * fb;
+            sa += wf * (1.0 + P);
+            sz += wf * (c1 * ez + c2 * eu * ez - c3 * uz);
+            sx += wf * (c1 * ex + c2 * eu * ex - c3 * ux);
+        }
+        Ab[k] = om * sa;
+        uzb += om * A[k] * sz;
+        uxb += om * A[k] * sx;
+    }
+    // forcing adjoint (F_0 = 0)
+    const double fzb = a.s_fz[y], fxb = a.s_fx[y];
+    double nb = -fzb * (nf.ez + ux * nf.by) - fxb * (nf.ex - uz * nf.by);
+    uxb += -n * nf.by * fzb;
+    uzb += n * nf.by * fxb;
+    a.s_enz[y] = -n * fzb;
+    a.s_enx[y] = -n * fxb;
+    a.s_bny[y] = -n * (ux * fzb - uz * fxb);
+    // phi at y is read by d_z at (j, i - 1) (as i + 1) and (j, i + 1) (as i - 1)
+    const double k2 = a.mu / (2.0 * a.delta);
+    const double phib = -k2 * (gather2(a.s_fz, jy, iy, 0, 1, false, false, nx, nz, bx, bz) -
+                               gather2(a.s_fz, jy, iy, 0, -1, false, false, nx, nz, bx, bz)) -
+                        k2 * (gather2(a.s_fx, jy, iy, 1, 0, false, false, nx, nz, bx, bz) -
+                              gather2(a.s_fx, jy, iy, -1, 0, false, false, nx, nz, bx, bz));
+    double Rb[3];
+    lec_recover_adj(J, uzb, uxb, phib, nb, 1.0 + a.two_over_d, Rb);
+    const double keep = 1.0 - om;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double tot = Ab[k] + Rb[k];
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            a.lf[(size_t)(k * 9 + q) * nc + y] = keep * a.s_fs[(size_t)(k * 9 + q) * nc + y] + tot;
+    }
+}
+
+// (d1) Adjoint of Bh at every staggered slot: from B' (S9) and from the
+// 4-point node average of S3; it is also the adjoint of B^{n-1/2}.
+__global__ void k_adj_bh(AdjArgs a)
+{
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.ncell) return;
+    const int iy = y % a.nz, jy = y / a.nz;
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    double b = a.s_byt[y];
+    b += 0.25 * (gather2(a.s_bny, jy, iy, 0, 0, true, true, nx, nz, bx, bz) +
+                 gather2(a.s_bny, jy, iy, 0, -1, true, true, nx, nz, bx, bz) +
+                 gather2(a.s_bny, jy, iy, -1, 0, true, true, nx, nz, bx, bz) +
+                 gather2(a.s_bny, jy, iy, -1, -1, true, true, nx, nz, bx, bz));
+    a.s_bht[y] = b;
+}
+
+// (d2) Adjoint of E^n (identity, node averages, and the two dt/2 curls of S3
+// and S9) and of B^{n-1/2}; s_col holds X = adjoint(B') + adjoint(Bh).
+__global__ void k_adj_fields(AdjArgs a)
+{
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.ncell) return;
+    const int iy = y % a.nz, jy = y / a.nz;
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    const double hdi = 0.5 * a.dt / a.delta;
+    const double *X = a.s_col;
+    // E_z slot (x node, z staggered): read by En_z at (j, i + 1) as i - 1 and at
+    // (j, i); by curlE at (j - 1, i) as j + 1 (minus) and at (j, i) (plus)
+    double ez = a.lez[y];
+    ez += 0.5 * (gather2(a.s_enz, jy, iy, 0, -1, false, true, nx, nz, bx, bz) +
+                 gather2(a.s_enz, jy, iy, 0, 0, false, true, nx, nz, bx, bz));
+    ez -= hdi * (-gather2(X, jy, iy, 1, 0, false, true, nx, nz, bx, bz) +
+                 gather2(X, jy, iy, 0, 0, false, true, nx, nz, bx, bz));
+    // E_x slot (x staggered, z node)
+    double ex = a.lex[y];
+    ex += 0.5 * (gather2(a.s_enx, jy, iy, -1, 0, true, false, nx, nz, bx, bz) +
+                 gather2(a.s_enx, jy, iy, 0, 0, true, false, nx, nz, bx, bz));
+    ex -= hdi * (gather2(X, jy, iy, 0, 1, true, false, nx, nz, bx, bz) -
+                 gather2(X, jy, iy, 0, 0, true, false, nx, nz, bx, bz));
+    a.lez[y] = ez;
+    a.lex[y] = ex;
+    a.lby[y] = a.s_bht[y];
+}
+
+__global__ void k_adj_sum_bx(AdjArgs a)
+{
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.ncell) return;
+    a.s_col[y] = a.s_byt[y] + a.s_bht[y];
+}
+
+// Slice derivatives of the driver current: E'_z gains dt n_b at
+// ((i + 1/2) delta, x_j, t^{n+1/2}), n_b = alpha w_s exp(-e). Column sums over
+// x first (one thread per column), then one thread per slice adds its columns
+// in a fixed order.
+__global__ void k_adj_drv_cols(AdjArgs a, const double *lez, double t, double zoff, double *col)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nz) return;
+    const Driver &d = a.drv;
+    double acc = 0.0;
+    for (int j = 0; j < a.nx; ++j) {
+        const double xx = (j - 0.5 * (a.nx - 1)) * a.delta - d.x0;
+        const double zeta = (i + zoff) * a.delta - d.z0 - t;
+        const double e = zeta * zeta * d.inv2sz2 + xx * xx * d.inv2sx2;
+        if (e > 746.0) continue;
+        acc += lez[(size_t)j * a.nz + i] * exp(-e);
+    }
+    col[i] = acc;
+}
+
+// Initial fields: E_x(j, i) = g(zeta_e) tr(j), B_y(j, i) = g(zeta_b) tr(j) with
+// g = alpha w_s exp(-zeta^2 / 2 sigma_z^2); per column sum_j lambda tr(j).
+__global__ void k_adj_init_cols(AdjArgs a, const double *lam, double *col)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nz) return;
+    const Driver &d = a.drv;
+    double acc = 0.0;
+    for (int j = 0; j < a.nx; ++j) {
+        const double xh = (j + 0.5 - 0.5 * (a.nx - 1)) * a.delta - d.x0;
+        const double tr = -d.sigma_x * sqrt(M_PI / 2.0) * erf(xh / (sqrt(2.0) * d.sigma_x));
+        acc += lam[(size_t)j * a.nz + i] * tr;
+    }
+    col[i] = acc;
+}
+
+// grad[s] += scale * sum over columns i in slice s of col[i] * shape(zeta_i);
+// shape = alpha exp(-zeta^2 / (2 sigma_z^2)) (with_exp) or alpha (the x and z
+// Gaussians already inside col).
+__global__ void k_adj_slices(AdjArgs a, const double *col, double t, double zoff, double scale, int with_exp)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const Driver &d = a.drv;
+    if (s >= d.nslices) return;
+    double acc = 0.0;
+    for (int i = 0; i < a.nz; ++i) {
+        const double zeta = (i + zoff) * a.delta - d.z0 - t;
+        if (!(zeta >= d.slice_zmin && zeta < d.slice_zmax)) continue;
+        int k = (int)floor((zeta - d.slice_zmin) / (d.slice_zmax - d.slice_zmin) * d.nslices);
+        k = k < 0 ? 0 : (k >= d.nslices ? d.nslices - 1 : k);
+        if (k != s) continue;
+        acc += col[i] * (with_exp ? exp(-zeta * zeta * d.inv2sz2) : 1.0);
+    }
+    a.grad[s] += scale * d.alpha * acc;
+}
+
+}  // namespace lbw

@@ -4,6 +4,7 @@
 // bookkeeping around it.
 #include "../../include/lbwake.h"
 #include "lbw_kernels.hpp"
+#include "lbw_adjoint.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -753,6 +754,176 @@ lbw_status lbw_load_state(lbw_sim *s, const void *host, size_t bytes)
     s->lag_valid = h.lag_valid != 0;
     s->canonical = true;
     s->initialized = true;
+    return LBW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device-side copies of the canonical state, and the discrete adjoint.
+namespace {
+struct DevStateLayout {
+    size_t pop, fld[3], lag, total;
+};
+DevStateLayout dev_state_layout(const lbw_sim *s)
+{
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    DevStateLayout d{};
+    size_t off = 0;
+    d.pop = off; off += align_up(nc * s->L.K * s->L.Q * storage_size(s->g.storage));
+    for (int f = 0; f < 3; ++f) { d.fld[f] = off; off += align_up(nc * 8); }
+    d.lag = off; off += align_up((size_t)nlag(s->g.dims, s->g.closure) * nc * 8);
+    d.total = off;
+    return d;
+}
+constexpr int ADJ_SCRATCH_PLANES = 8;  // B' adjoint, F_z, F_x, En_z, En_x, Bn_y, Bh, sum
+}  // namespace
+
+size_t lbw_state_device_bytes(const lbw_sim *s) { return s ? dev_state_layout(s).total : 0; }
+
+lbw_status lbw_save_state_device(lbw_sim *s, void *dev)
+{
+    if (!s || !dev) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (((uintptr_t)dev % ALIGN) != 0) return fail(s, LBW_ERR_ARG, "device buffer must be 256-byte aligned");
+    const DevStateLayout d = dev_state_layout(s);
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    char *p = (char *)dev;
+    HIPCHK(s, hipMemcpyAsync(p + d.pop, s->ws + s->L.pop[s->pcur], nc * s->L.K * s->L.Q * storage_size(s->g.storage),
+                             hipMemcpyDeviceToDevice, s->stream));
+    for (int f = 0; f < 3; ++f)
+        HIPCHK(s, hipMemcpyAsync(p + d.fld[f], s->ws + s->L.fld[s->fcur][f], nc * 8, hipMemcpyDeviceToDevice,
+                                 s->stream));
+    const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
+    if (lagb) HIPCHK(s, hipMemcpyAsync(p + d.lag, s->ws + s->L.lag, lagb, hipMemcpyDeviceToDevice, s->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_load_state_device(lbw_sim *s, const void *dev, long step)
+{
+    if (!s || !dev) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (((uintptr_t)dev % ALIGN) != 0) return fail(s, LBW_ERR_ARG, "device buffer must be 256-byte aligned");
+    if (step < 0) return fail(s, LBW_ERR_ARG, "step must be >= 0");
+    const DevStateLayout d = dev_state_layout(s);
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    const char *p = (const char *)dev;
+    s->pcur = s->fcur = 0;
+    HIPCHK(s, hipMemcpyAsync(s->ws + s->L.pop[0], p + d.pop, nc * s->L.K * s->L.Q * storage_size(s->g.storage),
+                             hipMemcpyDeviceToDevice, s->stream));
+    for (int f = 0; f < 3; ++f)
+        HIPCHK(s, hipMemcpyAsync(s->ws + s->L.fld[0][f], p + d.fld[f], nc * 8, hipMemcpyDeviceToDevice, s->stream));
+    const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
+    if (lagb) HIPCHK(s, hipMemcpyAsync(s->ws + s->L.lag, p + d.lag, lagb, hipMemcpyDeviceToDevice, s->stream));
+    s->step = step;
+    s->lag_valid = step > 0;
+    s->canonical = true;
+    return LBW_OK;
+}
+
+size_t lbw_adjoint_bytes(const lbw_sim *s)
+{
+    if (!s) return 0;
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    return ((size_t)s->L.K * s->L.Q + 3) * nc * 8;
+}
+
+size_t lbw_adjoint_workspace_bytes(const lbw_sim *s)
+{
+    if (!s) return 0;
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    return ((size_t)s->L.K * s->L.Q + ADJ_SCRATCH_PLANES) * align_up(nc * 8) + align_up((size_t)s->g.nz * 8);
+}
+
+static lbw_status adj_args(lbw_sim *s, double *adj, double *grad, void *scratch, AdjArgs &a)
+{
+    if (!s || !adj || !grad || !scratch) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (s->g.dims != 2 || s->g.closure != LBW_LEC)
+        return fail(s, LBW_ERR_UNSUPPORTED, "the adjoint covers the 2D local-equilibrium closure");
+    if (s->drv.nslices <= 0) return fail(s, LBW_ERR_STATE, "the driver has no slices to differentiate");
+    if (((uintptr_t)scratch % ALIGN) != 0) return fail(s, LBW_ERR_ARG, "scratch must be 256-byte aligned");
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    a = AdjArgs{};
+    a.lf = adj;
+    a.lez = adj + (size_t)s->L.K * s->L.Q * nc;
+    a.lex = a.lez + nc;
+    a.lby = a.lex + nc;
+    char *p = (char *)scratch;
+    const size_t pl = align_up(nc * 8);
+    a.s_fs = (double *)p; p += (size_t)s->L.K * s->L.Q * pl;
+    double *pls[ADJ_SCRATCH_PLANES];
+    for (int k = 0; k < ADJ_SCRATCH_PLANES; ++k) { pls[k] = (double *)p; p += pl; }
+    a.s_byt = pls[0]; a.s_fz = pls[1]; a.s_fx = pls[2]; a.s_enz = pls[3]; a.s_enx = pls[4];
+    a.s_bny = pls[5]; a.s_bht = pls[6]; a.s_col = pls[7];
+    a.aref = (const double *)(s->ws + s->L.aref);
+    a.grad = grad;
+    a.nz = s->g.nz; a.nx = s->g.nx; a.ncell = (int)nc; a.bcz = s->g.bc_z; a.bcx = s->g.bc_x;
+    a.delta = s->g.delta; a.dt = s->g.dt; a.omega = 1.0 / s->g.tau_tilde; a.lam = s->g.delta / s->g.dt;
+    a.mu = s->mu; a.a_lec = (1.0 + 0.5 * s->g.dvel) * s->mu; a.two_over_d = 2.0 / s->g.dvel;
+    a.dvel = s->g.dvel;
+    a.dcode = s->g.dvel == 1.0 ? 1 : (s->g.dvel == 3.0 ? 3 : 0);
+    a.drv = s->drv;
+    return LBW_OK;
+}
+
+extern "C++" {
+template <class ST>
+static void adj_step_launch(const AdjArgs &a, double *col, hipStream_t st)
+{
+    const int nb = (a.ncell + 255) / 256, nbz = (a.nz + 255) / 256;
+    const int nbs = (a.drv.nslices + 63) / 64;
+    hipLaunchKernelGGL((k_adj_maxwell<ST>), dim3(nb), dim3(256), 0, st, a);
+    // slice derivatives read the adjoint of E^{n+1} before it is overwritten
+    const double th = (a.step + 0.5) * a.dt;
+    hipLaunchKernelGGL(k_adj_drv_cols, dim3(nbz), dim3(256), 0, st, a, (const double *)a.lez, th, 0.5, col);
+    hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, st, a, (const double *)col, th, 0.5, a.dt, 0);
+    hipLaunchKernelGGL(k_adj_stream, dim3(nb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_adj_collide<ST>), dim3(nb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_bh, dim3(nb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_sum_bx, dim3(nb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_fields, dim3(nb), dim3(256), 0, st, a);
+}
+}  // extern "C++"
+
+lbw_status lbw_adjoint_step(lbw_sim *s, const void *state_n, const void *state_n1, long n, double *adj,
+                            double *grad, void *scratch)
+{
+    AdjArgs a;
+    lbw_status rc = adj_args(s, adj, grad, scratch, a);
+    if (rc != LBW_OK) return rc;
+    if (!state_n || !state_n1) return fail(s, LBW_ERR_ARG, "NULL state");
+    if (n < 0) return fail(s, LBW_ERR_ARG, "step must be >= 0");
+    const DevStateLayout d = dev_state_layout(s);
+    const char *p0 = (const char *)state_n, *p1 = (const char *)state_n1;
+    a.fn = p0 + d.pop;
+    a.fn1 = p1 + d.pop;
+    a.ez = (const double *)(p0 + d.fld[0]);
+    a.ex = (const double *)(p0 + d.fld[1]);
+    a.by = (const double *)(p0 + d.fld[2]);
+    a.step = n;
+    double *col = (double *)((char *)scratch + ((size_t)s->L.K * s->L.Q + ADJ_SCRATCH_PLANES) *
+                                                   align_up((size_t)a.ncell * 8));
+    if (s->g.storage == LBW_FP64) adj_step_launch<double>(a, col, s->stream);
+    else if (s->g.storage == LBW_FP32) adj_step_launch<float>(a, col, s->stream);
+    else adj_step_launch<__half>(a, col, s->stream);
+    HIPCHK(s, hipGetLastError());
+    return LBW_OK;
+}
+
+lbw_status lbw_adjoint_init_fields(lbw_sim *s, const double *adj, double *grad, void *scratch)
+{
+    AdjArgs a;
+    lbw_status rc = adj_args(s, (double *)adj, grad, scratch, a);
+    if (rc != LBW_OK) return rc;
+    double *col = (double *)((char *)scratch + ((size_t)s->L.K * s->L.Q + ADJ_SCRATCH_PLANES) *
+                                                   align_up((size_t)a.ncell * 8));
+    const int nbz = (a.nz + 255) / 256, nbs = (a.drv.nslices + 63) / 64;
+    // E_x(0) at zeta = i delta - z0; B_y(-dt/2) at zeta = (i + 1/2) delta - z0 + dt/2
+    hipLaunchKernelGGL(k_adj_init_cols, dim3(nbz), dim3(256), 0, s->stream, a, (const double *)a.lex, col);
+    hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, s->stream, a, (const double *)col, 0.0, 0.0, 1.0, 1);
+    hipLaunchKernelGGL(k_adj_init_cols, dim3(nbz), dim3(256), 0, s->stream, a, (const double *)a.lby, col);
+    hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, s->stream, a, (const double *)col, -0.5 * a.dt, 0.5,
+                       1.0, 1);
+    HIPCHK(s, hipGetLastError());
     return LBW_OK;
 }
 

@@ -155,6 +155,23 @@ class Sim:
         self._check(self._lib.lbw_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    # device-side checkpoints (torch uint8 tensors on the simulation's device)
+    def state_device_bytes(self):
+        return int(self._lib.lbw_state_device_bytes(self._h))
+
+    def save_state_device(self, out=None):
+        import torch
+
+        n = self.state_device_bytes()
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self._check(self._lib.lbw_save_state_device(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def load_state_device(self, buf, step):
+        self._check(self._lib.lbw_load_state_device(self._h, ctypes.c_void_p(buf.data_ptr()), int(step)))
+        return self
+
     def save_state(self) -> bytes:
         n = self._lib.lbw_state_bytes(self._h)
         buf = ctypes.create_string_buffer(n)
