@@ -170,6 +170,74 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+# Algorithmic bytes per node of one reverse step of the adjoint (FP64 adjoint
+# state, populations of the saved forward states in the storage type): each
+# kernel's reads and writes of full planes, K*Q = 27 population planes.
+def adjoint_bytes_per_node(storage):
+    sb = {"fp64": 8, "fp32": 4, "fp16dev": 2}[storage]
+    P = 27
+    maxwell = 3 * 8 + P * sb + 2 * P * 8 + 8       # adj E, B; f^{n+1}; adj f (+=); adj B'
+    stream = P * 8 + P * 8 + 2 * 8                  # adj f -> adj f*, adj F
+    collide = P * sb + 3 * 8 + P * 8 + 2 * 8 + P * 8 + 3 * 8
+    bh = 2 * 8 + 8                                  # adj Bh from adj B' and adj Bn_y
+    xsum = 2 * 8 + 8
+    fields = 6 * 8 + 3 * 8                          # adj E^n, B^{n-1/2}
+    return maxwell + stream + collide + bh + xsum + fields
+
+
+def bench_adjoint(args):
+    import torch
+
+    from paper_2309_04872_amd import adjoint, workloads
+
+    storage = args.storage or "fp32"
+    cfg = adjoint.adjoint_config(storage=storage)
+    if args.steps is not None:
+        cfg["steps"] = args.steps
+    w = workloads.slice_weights(64, 0.5, 1.5, 0)
+    cells = cfg["nz"] * cfg["nx"]
+    if args.warmup:  # one untimed gradient of the same workload
+        adjoint.loss_and_grad(cfg, w, every=100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, g = adjoint.loss_and_grad(cfg, w, every=100, timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = adjoint.last_timing()
+    step_s = tm["adjoint_ms"] / tm["adjoint_steps"] / 1e3
+    bpn = adjoint_bytes_per_node(storage)
+    achieved = bpn * cells / step_s / 1e9
+    line = {
+        "metric": "MLUPS (LB+field)",
+        "value": cells * cfg["steps"] / wall / 1e6,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": cfg["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / cfg["steps"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16"}[storage],
+        "data": "synthetic",
+        "config": {
+            "workload": "wake2d_lec_adjoint", "nz": cfg["nz"], "nx": cfg["nx"], "closure": "lec",
+            "populations": storage, "adjoint": "f64", "slices": 64, "checkpoint_every": 100,
+            "what": "one gradient: forward with checkpoints, recompute, reverse steps",
+            "delta": "lambda_p/64", "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "reverse step (8 kernels)",
+            "kernel_avg_us": step_s * 1e6, "bytes_per_node": bpn,
+        },
+        "wall_s": wall,
+        "phases_ms": tm,
+        "loss": loss, "grad_norm": float(np.linalg.norm(g)),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +255,8 @@ def main():
 
     if args.workload == "batch1d_scan":
         return bench_batch(args)
+    if args.workload == "wake2d_lec_adjoint":
+        return bench_adjoint(args)
 
     import torch
 

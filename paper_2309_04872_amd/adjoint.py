@@ -59,18 +59,38 @@ def forward_loss(cfg, weights):
     return r.loss()
 
 
-def loss_and_grad(cfg, weights, every=100, grad_out=1.0):
-    """Loss and d loss / d weights (numpy), checkpoints every ``every`` steps."""
+_TIMING = {}
+
+
+def last_timing():
+    """Phase times (ms) of the last loss_and_grad(..., timing=True)."""
+    return dict(_TIMING)
+
+
+def loss_and_grad(cfg, weights, every=100, grad_out=1.0, timing=False):
+    """Loss and d loss / d weights (numpy), checkpoints every ``every`` steps.
+    timing: record HIP events on the simulation's stream around the forward,
+    the recompute and the reverse steps (last_timing())."""
     import torch
 
     r = _Run(cfg, weights).start()
     sim, lib, h = r.sim, r.sim._lib, r.sim._h
     steps = cfg["steps"]
     sb = sim.state_device_bytes()
+    ev = {}
+
+    def mark(name):
+        if timing:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(sim.stream)
+            ev.setdefault(name, []).append(e)
+
     ckpt = {}
+    mark("fwd0")
     for n0 in range(0, steps, every):
         ckpt[n0] = sim.save_state_device()
         sim.step(min(every, steps - n0))
+    mark("fwd1")
     loss = r.loss()
 
     dev = sim.device
@@ -92,17 +112,27 @@ def loss_and_grad(cfg, weights, every=100, grad_out=1.0):
 
     for n0 in sorted(ckpt, reverse=True):
         n1 = min(n0 + every, steps)
+        mark("rec0")
         sim.load_state_device(ckpt[n0], n0)
         sim.save_state_device(buf[0:sb])
         for m in range(1, n1 - n0 + 1):
             sim.step(1)
             sim.save_state_device(buf[m * sb:(m + 1) * sb])
+        mark("rec1")
+        mark("adj0")
         for n in range(n1 - 1, n0 - 1, -1):
             m = n - n0
             check(lib.lbw_adjoint_step(h, vp(buf[m * sb:].data_ptr()), vp(buf[(m + 1) * sb:].data_ptr()), n,
                                        vp(adj.data_ptr()), vp(grad.data_ptr()), vp(scratch.data_ptr())))
+        mark("adj1")
     check(lib.lbw_adjoint_init_fields(h, vp(adj.data_ptr()), vp(grad.data_ptr()), vp(scratch.data_ptr())))
     torch.cuda.synchronize(dev)
+    if timing:
+        def total(a, b):
+            return sum(x.elapsed_time(y) for x, y in zip(ev[a], ev[b]))
+        _TIMING.clear()
+        _TIMING.update(forward_ms=total("fwd0", "fwd1"), recompute_ms=total("rec0", "rec1"),
+                       adjoint_ms=total("adj0", "adj1"), adjoint_steps=steps)
     return loss, grad.cpu().numpy()
 
 

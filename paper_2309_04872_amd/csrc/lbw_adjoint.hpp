@@ -148,7 +148,7 @@ __device__ __forceinline__ void moments3(const void *f, const AdjArgs &a, size_t
 // (a) Reverse of S9 and S8 at every slot/node y: adjoint of B', the currents'
 // adjoint m'b, through the recovery at n+1 into the adjoint of f'.
 template <class ST>
-__global__ void k_adj_maxwell(AdjArgs a)
+__global__ __launch_bounds__(256) void k_adj_maxwell(AdjArgs a)
 {
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= a.ncell) return;
@@ -184,7 +184,7 @@ __global__ void k_adj_maxwell(AdjArgs a)
 
 // (b) Reverse of S7 (streaming): adjoint of f* gathered from the nodes that
 // pulled from y; adjoint of the forcing F_k = dt sum_q w_q fs_b.
-__global__ void k_adj_stream(AdjArgs a)
+__global__ __launch_bounds__(256) void k_adj_stream(AdjArgs a)
 {
     using L = Lattice<2>;
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
@@ -244,7 +244,7 @@ __device__ __forceinline__ NodeF node_fields_at(const AdjArgs &a, int j, int i)
 // of phi gathers the forcing adjoint of the neighbours), recovery; writes
 // the adjoint of f^n and the node-field adjoints.
 template <class ST>
-__global__ void k_adj_collide(AdjArgs a)
+__global__ __launch_bounds__(256) void k_adj_collide(AdjArgs a)
 {
     using L = Lattice<2>;
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,7 +262,9 @@ __global__ void k_adj_collide(AdjArgs a)
     const double c1 = 3.0 / lam, c2 = 9.0 / (lam * lam), c3 = 3.0 / (lam * lam);
     // collision adjoint
     double Ab[3], uzb = 0.0, uxb = 0.0;
-#pragma unroll
+    // one scalar at a time keeps the register count low enough for 4 waves
+    // per SIMD; the second pass below re-reads the same values from cache
+#pragma unroll 1
     for (int k = 0; k < 3; ++k) {
         double sa = 0.0, sz = 0.0, sx = 0.0;
 #pragma unroll
@@ -308,7 +310,7 @@ __global__ void k_adj_collide(AdjArgs a)
 
 // (d1) Adjoint of Bh at every staggered slot: from B' (S9) and from the
 // 4-point node average of S3; it is also the adjoint of B^{n-1/2}.
-__global__ void k_adj_bh(AdjArgs a)
+__global__ __launch_bounds__(256) void k_adj_bh(AdjArgs a)
 {
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= a.ncell) return;
@@ -324,7 +326,7 @@ __global__ void k_adj_bh(AdjArgs a)
 
 // (d2) Adjoint of E^n (identity, node averages, and the two dt/2 curls of S3
 // and S9) and of B^{n-1/2}; s_col holds X = adjoint(B') + adjoint(Bh).
-__global__ void k_adj_fields(AdjArgs a)
+__global__ __launch_bounds__(256) void k_adj_fields(AdjArgs a)
 {
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= a.ncell) return;
@@ -350,7 +352,7 @@ __global__ void k_adj_fields(AdjArgs a)
     a.lby[y] = a.s_bht[y];
 }
 
-__global__ void k_adj_sum_bx(AdjArgs a)
+__global__ __launch_bounds__(256) void k_adj_sum_bx(AdjArgs a)
 {
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= a.ncell) return;
@@ -358,51 +360,66 @@ __global__ void k_adj_sum_bx(AdjArgs a)
 }
 
 // Slice derivatives of the driver current: E'_z gains dt n_b at
-// ((i + 1/2) delta, x_j, t^{n+1/2}), n_b = alpha w_s exp(-e). Column sums over
-// x first (one thread per column), then one thread per slice adds its columns
-// in a fixed order.
-__global__ void k_adj_drv_cols(AdjArgs a, const double *lez, double t, double zoff, double *col)
+// ((i + 1/2) delta, x_j, t^{n+1/2}), n_b = alpha w_s exp(-e). One workgroup per
+// column of the bunch window [i0, i0 + gridDim.x) sums over x (tree
+// reduction, fixed order); then one thread per slice adds its columns in
+// order.
+__global__ __launch_bounds__(256) void k_adj_drv_cols(AdjArgs a, const double *lez, double t, double zoff, int i0,
+                                                      double *col)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.nz) return;
+    __shared__ double red[256];
+    const int i = i0 + blockIdx.x;
     const Driver &d = a.drv;
+    const double zeta = (i + zoff) * a.delta - d.z0 - t;
+    const double ez2 = zeta * zeta * d.inv2sz2;
     double acc = 0.0;
-    for (int j = 0; j < a.nx; ++j) {
+    for (int j = threadIdx.x; j < a.nx; j += blockDim.x) {
         const double xx = (j - 0.5 * (a.nx - 1)) * a.delta - d.x0;
-        const double zeta = (i + zoff) * a.delta - d.z0 - t;
-        const double e = zeta * zeta * d.inv2sz2 + xx * xx * d.inv2sx2;
-        if (e > 746.0) continue;
-        acc += lez[(size_t)j * a.nz + i] * exp(-e);
+        const double e = ez2 + xx * xx * d.inv2sx2;
+        if (e <= 746.0) acc += lez[(size_t)j * a.nz + i] * exp(-e);
     }
-    col[i] = acc;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) col[i] = red[0];
 }
 
 // Initial fields: E_x(j, i) = g(zeta_e) tr(j), B_y(j, i) = g(zeta_b) tr(j) with
 // g = alpha w_s exp(-zeta^2 / 2 sigma_z^2); per column sum_j lambda tr(j).
-__global__ void k_adj_init_cols(AdjArgs a, const double *lam, double *col)
+__global__ __launch_bounds__(256) void k_adj_init_cols(AdjArgs a, const double *lam, int i0, double *col)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.nz) return;
+    __shared__ double red[256];
+    const int i = i0 + blockIdx.x;
     const Driver &d = a.drv;
     double acc = 0.0;
-    for (int j = 0; j < a.nx; ++j) {
+    for (int j = threadIdx.x; j < a.nx; j += blockDim.x) {
         const double xh = (j + 0.5 - 0.5 * (a.nx - 1)) * a.delta - d.x0;
         const double tr = -d.sigma_x * sqrt(M_PI / 2.0) * erf(xh / (sqrt(2.0) * d.sigma_x));
         acc += lam[(size_t)j * a.nz + i] * tr;
     }
-    col[i] = acc;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) col[i] = red[0];
 }
 
-// grad[s] += scale * sum over columns i in slice s of col[i] * shape(zeta_i);
-// shape = alpha exp(-zeta^2 / (2 sigma_z^2)) (with_exp) or alpha (the x and z
-// Gaussians already inside col).
-__global__ void k_adj_slices(AdjArgs a, const double *col, double t, double zoff, double scale, int with_exp)
+// grad[s] += scale * alpha * sum over the window's columns i in slice s of
+// col[i] (times exp(-zeta^2 / (2 sigma_z^2)) when with_exp: the initial
+// fields, whose column sums hold only the x profile).
+__global__ void k_adj_slices(AdjArgs a, const double *col, double t, double zoff, int i0, int i1, double scale,
+                             int with_exp)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const Driver &d = a.drv;
     if (s >= d.nslices) return;
     double acc = 0.0;
-    for (int i = 0; i < a.nz; ++i) {
+    for (int i = i0; i < i1; ++i) {
         const double zeta = (i + zoff) * a.delta - d.z0 - t;
         if (!(zeta >= d.slice_zmin && zeta < d.slice_zmax)) continue;
         int k = (int)floor((zeta - d.slice_zmin) / (d.slice_zmax - d.slice_zmin) * d.nslices);

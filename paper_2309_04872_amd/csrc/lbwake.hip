@@ -866,16 +866,34 @@ static lbw_status adj_args(lbw_sim *s, double *adj, double *grad, void *scratch,
 }
 
 extern "C++" {
+// Columns [i0, i1) of the grid that can hold the slice span at time t for
+// positions (i + zoff) delta (one column of margin each side).
+static void slice_window(const AdjArgs &a, double t, double zoff, int &i0, int &i1)
+{
+    const double lo = (a.drv.slice_zmin + a.drv.z0 + t) / a.delta - zoff;
+    const double hi = (a.drv.slice_zmax + a.drv.z0 + t) / a.delta - zoff;
+    i0 = (int)std::floor(lo) - 1;
+    i1 = (int)std::ceil(hi) + 2;
+    i0 = i0 < 0 ? 0 : (i0 > a.nz ? a.nz : i0);
+    i1 = i1 < i0 ? i0 : (i1 > a.nz ? a.nz : i1);
+}
+
 template <class ST>
 static void adj_step_launch(const AdjArgs &a, double *col, hipStream_t st)
 {
-    const int nb = (a.ncell + 255) / 256, nbz = (a.nz + 255) / 256;
+    const int nb = (a.ncell + 255) / 256;
     const int nbs = (a.drv.nslices + 63) / 64;
     hipLaunchKernelGGL((k_adj_maxwell<ST>), dim3(nb), dim3(256), 0, st, a);
     // slice derivatives read the adjoint of E^{n+1} before it is overwritten
     const double th = (a.step + 0.5) * a.dt;
-    hipLaunchKernelGGL(k_adj_drv_cols, dim3(nbz), dim3(256), 0, st, a, (const double *)a.lez, th, 0.5, col);
-    hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, st, a, (const double *)col, th, 0.5, a.dt, 0);
+    int i0, i1;
+    slice_window(a, th, 0.5, i0, i1);
+    if (i1 > i0) {
+        hipLaunchKernelGGL(k_adj_drv_cols, dim3(i1 - i0), dim3(256), 0, st, a, (const double *)a.lez, th, 0.5, i0,
+                           col);
+        hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, st, a, (const double *)col, th, 0.5, i0, i1, a.dt,
+                           0);
+    }
     hipLaunchKernelGGL(k_adj_stream, dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_adj_collide<ST>), dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_adj_bh, dim3(nb), dim3(256), 0, st, a);
@@ -916,13 +934,23 @@ lbw_status lbw_adjoint_init_fields(lbw_sim *s, const double *adj, double *grad, 
     if (rc != LBW_OK) return rc;
     double *col = (double *)((char *)scratch + ((size_t)s->L.K * s->L.Q + ADJ_SCRATCH_PLANES) *
                                                    align_up((size_t)a.ncell * 8));
-    const int nbz = (a.nz + 255) / 256, nbs = (a.drv.nslices + 63) / 64;
+    const int nbs = (a.drv.nslices + 63) / 64;
     // E_x(0) at zeta = i delta - z0; B_y(-dt/2) at zeta = (i + 1/2) delta - z0 + dt/2
-    hipLaunchKernelGGL(k_adj_init_cols, dim3(nbz), dim3(256), 0, s->stream, a, (const double *)a.lex, col);
-    hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, s->stream, a, (const double *)col, 0.0, 0.0, 1.0, 1);
-    hipLaunchKernelGGL(k_adj_init_cols, dim3(nbz), dim3(256), 0, s->stream, a, (const double *)a.lby, col);
-    hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, s->stream, a, (const double *)col, -0.5 * a.dt, 0.5,
-                       1.0, 1);
+    int i0, i1;
+    slice_window(a, 0.0, 0.0, i0, i1);
+    if (i1 > i0) {
+        hipLaunchKernelGGL(k_adj_init_cols, dim3(i1 - i0), dim3(256), 0, s->stream, a, (const double *)a.lex, i0,
+                           col);
+        hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, s->stream, a, (const double *)col, 0.0, 0.0, i0,
+                           i1, 1.0, 1);
+    }
+    slice_window(a, -0.5 * a.dt, 0.5, i0, i1);
+    if (i1 > i0) {
+        hipLaunchKernelGGL(k_adj_init_cols, dim3(i1 - i0), dim3(256), 0, s->stream, a, (const double *)a.lby, i0,
+                           col);
+        hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, s->stream, a, (const double *)col, -0.5 * a.dt,
+                           0.5, i0, i1, 1.0, 1);
+    }
     HIPCHK(s, hipGetLastError());
     return LBW_OK;
 }
