@@ -166,7 +166,8 @@ __device__ __forceinline__ double driver_density(const Driver &d, double z, doub
 //         G(d) = d S h^2 - P^2 = (p h)^2 - P^2 = 0, increasing in d;
 //         no root or cube root inside the loop, quadratic convergence from the
 //         lower bound p = P / (1 + b); stopped once a step falls below 1e-12 d,
-//         at most 12 passes, else bisection.
+//         at most 12 passes, else bisection. Quotients use rcp64 (hardware
+//         reciprocal estimate plus two Newton-Raphson corrections).
 //  other D: the fixed point with pow().
 // Returns false when a fallback was needed.
 struct LecRec {
@@ -185,18 +186,32 @@ __device__ __forceinline__ double lec_bisect(double n, double P, double a, int d
     return 0.5 * (lo + hi);
 }
 
+// 1/x to FP64 accuracy: the hardware estimate refined by two Newton-Raphson
+// corrections (no IEEE division sequence).
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ bool lec_recover(double n, double a1z, double a1x, double a_lec,
                                             int dcode, double two_over_d, LecRec &r)
 {
-    // |A_1| / n without squaring (squares of tiny momenta would underflow)
-    const double P = (a1x == 0.0 ? fabs(a1z) : hypot(a1z, a1x)) / n;
-    double p, g, n0, phi;
+    // |A_1| without squaring tiny momenta (their squares would underflow)
+    const double amax = fmax(fabs(a1z), fabs(a1x));
+    const double amag = a1x == 0.0 ? fabs(a1z) : (amax < 1e-150 ? hypot(a1z, a1x) : sqrt(a1z * a1z + a1x * a1x));
+    double p, g, n0, phi, ig = 1.0;
     bool ok = false;
     if (dcode == 3) {
+        const double in = rcp64(n);
+        const double P = amag * in;
         const double n23 = cbrt(n * n);
         const double b = a_lec * n23;
         const double P2 = P * P;
-        const double p0 = P / (1.0 + b);
+        const double p0 = P * rcp64(1.0 + b);
         double d = cbrt(sqrt(1.0 + p0 * p0)) - 1.0;
         // |p| < 1e-100: gamma = 1 far below rounding, p = P / (1 + b) exactly
         // (this also keeps subnormal P^2 out of the relative stopping test)
@@ -205,13 +220,13 @@ __device__ __forceinline__ bool lec_recover(double n, double a1z, double a1x, do
             ok = true;
         }
         for (int it = 0; it < 12 && !ok; ++it) {
-            const double c = 1.0 + d, ic = 1.0 / c;
+            const double c = 1.0 + d, ic = rcp64(c);
             const double S = 1.0 + c * (1.0 + c * (1.0 + c * (1.0 + c * (1.0 + c))));
             const double dS = 1.0 + c * (2.0 + c * (3.0 + c * (4.0 + 5.0 * c)));
             const double h = 1.0 + b * ic * ic;          // 1 + a (n / gamma)^{2/3}
             const double G = d * S * h * h - P2;          // (p h)^2 - P^2, increasing in d
             const double dG = (S + d * dS) * h * h - 4.0 * d * S * h * b * ic * ic * ic;
-            double dn = d - G / dG;
+            double dn = d - G * rcp64(dG);
             if (dn < 0.0) dn = 0.0;
             const double step = fabs(dn - d);
             d = dn;
@@ -222,25 +237,40 @@ __device__ __forceinline__ bool lec_recover(double n, double a1z, double a1x, do
                 break;
             }
         }
-        const double c = 1.0 + d, c2 = c * c;
+        const double c = 1.0 + d, ic = rcp64(c);
         const double S = 1.0 + c * (1.0 + c * (1.0 + c * (1.0 + c * (1.0 + c))));
+        // u = p_vec / gamma = A_1 p / (|A_1| gamma)
+        double scale;
         if (ok && P < 1e-100) {
+            // p / |A_1| = 1 / (n (1 + b)): no reciprocal of a |A_1| that may be subnormal
             p = p0;
             g = 1.0;
             n0 = n;
             phi = n0 * n23;
+            scale = in * rcp64(1.0 + b);
         } else if (ok) {
             p = sqrt(d * S);
-            g = c2 * c;
-            n0 = n / g;
-            phi = n0 * (n23 / c2);
+            g = c * c * c;
+            ig = ic * ic * ic;
+            n0 = n * ig;
+            phi = n0 * (n23 * (ic * ic));
+            scale = p * ig * rcp64(amag);  // |A_1| >= 1e-100 n here
         } else {
             p = lec_bisect(n, P, a_lec, dcode, two_over_d);
             g = sqrt(1.0 + p * p);
-            n0 = n / g;
+            ig = 1.0 / g;
+            n0 = n * ig;
             phi = n0 * cbrt(n0 * n0);
+            scale = P > 0.0 ? p / (P * n * g) : 0.0;
         }
+        r.uz = a1z * scale;
+        r.ux = a1x * scale;
+        r.gamma = g;
+        r.n0 = n0;
+        r.phi = phi;
+        return ok;
     } else {
+        const double P = amag / n;
         const double an2 = dcode == 1 ? a_lec * n * n : 0.0;
         p = P;
         for (int it = 0; it < 64; ++it) {
@@ -258,14 +288,14 @@ __device__ __forceinline__ bool lec_recover(double n, double a1z, double a1x, do
         g = sqrt(1.0 + p * p);
         n0 = n / g;
         phi = dcode == 1 ? n0 * n0 * n0 : n0 * pow(n0, two_over_d);
+        const double scale = P > 0.0 ? p / (P * n * g) : 0.0;  // u = p_vec / gamma
+        r.uz = a1z * scale;
+        r.ux = a1x * scale;
+        r.gamma = g;
+        r.n0 = n0;
+        r.phi = phi;
+        return ok;
     }
-    const double scale = P > 0.0 ? p / (P * n * g) : 0.0;  // u = p_vec / gamma
-    r.uz = a1z * scale;
-    r.ux = a1x * scale;
-    r.gamma = g;
-    r.n0 = n0;
-    r.phi = phi;
-    return ok;
 }
 
 // WARMC recovery (Sec. 4.1, App. A): lambda = (n lambda)/n, u from n lambda u,

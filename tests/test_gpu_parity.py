@@ -289,6 +289,8 @@ def test_lec_recovery_random_states(dims, D):
         # also tiny momenta (Gaussian tails ahead of a bunch) and, for D = 3,
         # strongly relativistic ones
         p[:, :, : nz // 8] *= 10.0 ** rng.uniform(-200, -5, size=(nx, nz // 8))
+        # and subnormal ones (FP64 storage reaches them far ahead of a bunch)
+        p[:, :, -(nz // 16):] *= 10.0 ** rng.uniform(-322, -300, size=(nx, nz // 16))
         if D == 3.0:
             p[:, :, nz // 8: nz // 4] *= 15.0
         if dims == 1:
