@@ -44,11 +44,11 @@ def bytes_per_lu(dims, closure, storage):
 # (the summaries and commands are in profiles/k_step2d_*.md). Valid for the
 # kernel as profiled; remove an entry when the kernel changes.
 TRAFFIC_BYTES_PER_LAUNCH = {
-    ("wake2d_lec_fp32", "fp32"): 302.1e6,
-    ("wake2d_lec_fp32", "fp64"): 622.3e6,
-    ("wake2d_warmc", "fp64"): 7238.8e6,
-    ("wake2d_warmc", "fp32"): 3922.0e6,
-    ("wake2d_warmc", "fp16dev"): 2111.7e6,
+    ("wake2d_lec_fp32", "fp32"): 301.6e6,
+    ("wake2d_lec_fp32", "fp64"): 605.6e6,
+    ("wake2d_warmc", "fp64"): 7254.5e6,
+    ("wake2d_warmc", "fp32"): 3914.4e6,
+    ("wake2d_warmc", "fp16dev"): 2108.9e6,
 }
 
 

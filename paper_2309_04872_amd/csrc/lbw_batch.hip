@@ -62,10 +62,10 @@ struct BatchArgs {
 };
 
 // LDS for the recovered quantities whose z-derivatives the forces need:
-// LEC phi | WARMC theta^0z, theta^zz, lambda u_z, on the pass plus one node
-// on each side.
+// LEC phi | WARMC theta^0z, theta^zz, lambda u_z, one value per slot of a
+// pass (its nodes plus one ring node on each side).
 template <int T, int CPT> struct Lds {
-    double g[3][T * CPT + 2];
+    double g[3][T * CPT];
     int bad;
 };
 
@@ -118,34 +118,34 @@ __device__ __forceinline__ void recover_node(const BInst &P, Node1<CL> &nd, Lds<
     }
 }
 
-// One pass of the fused step over nodes [base, base + T*CPT) of one instance.
+// Nodes a pass owns: each of the T*CPT slots recovers one node (slot r holds
+// node base - 1 + r), the first and last slots being the ring that the
+// forces' central differences need; the slots in between collide.
+template <int T, int CPT> constexpr int pass_width() { return T * CPT - 2; }
+
+// One pass of the fused step over nodes [base, base + pass_width) of one instance.
 template <int CL, int T, int CPT>
 __device__ __forceinline__ void step_pass(const BInst &P, const double *src, double *dst, double *ez,
                                           double *lag, int base, bool do_pull, bool do_maxwell,
                                           bool lag_init, long step, Lds<T, CPT> &sh)
 {
     constexpr int K = NScal<1, CL>::K;
-    constexpr int W = T * CPT;
+    constexpr int W = pass_width<T, CPT>();
     const int tid = threadIdx.x;
     const int nz = P.nz;
     const size_t nzp = (size_t)P.nzp;
-    if (tid < 2) {
-        Node1<CL> h;
-        const int r = tid == 0 ? 0 : W + 1;
-        pull_node<CL>(P, src, base - 1 + r, do_pull, h);
-        recover_node<CL, T, CPT>(P, h, sh, r);
-    }
     Node1<CL> nd[CPT];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) pull_node<CL>(P, src, base + tid + j * T, do_pull, nd[j]);
+    for (int j = 0; j < CPT; ++j) pull_node<CL>(P, src, base - 1 + tid + j * T, do_pull, nd[j]);
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) recover_node<CL, T, CPT>(P, nd[j], sh, 1 + tid + j * T);
+    for (int j = 0; j < CPT; ++j) recover_node<CL, T, CPT>(P, nd[j], sh, tid + j * T);
     __syncthreads();
     const double dt = P.dt;
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
-        const int gz = base + tid + j * T;
-        if (gz >= nz) continue;
+        const int slot = tid + j * T;
+        const int gz = base - 1 + slot;
+        if (slot < 1 || slot > W || gz >= nz) continue;
         Node1<CL> &v = nd[j];
         const double n = v.A[0], uz = v.uz;
         double Ez = ez[gz];
@@ -225,7 +225,8 @@ __device__ __forceinline__ int finish_pass(const BInst &P, const double *src, do
 template <int CL, int T, int CPT>
 __device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds<T, CPT> &sh)
 {
-    constexpr int W = T * CPT;
+    constexpr int W = pass_width<T, CPT>();
+    constexpr int WF = T * CPT;  // finish passes own every slot
     const int nsteps = a.nsteps;
     int cur = st->cur;
     const long step0 = st->step;
@@ -245,7 +246,7 @@ __device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds
     if (threadIdx.x == 0) sh.bad = 0;
     __syncthreads();
     int bad = 0;
-    for (int base = 0; base < P.nz; base += W)
+    for (int base = 0; base < P.nz; base += WF)
         bad += finish_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez, base, step0 + nsteps);
     if (bad) atomicAdd(&sh.bad, bad);
     __syncthreads();

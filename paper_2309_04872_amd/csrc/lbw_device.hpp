@@ -308,24 +308,27 @@ struct WarmRec {
 template <int DIM>
 __device__ __forceinline__ void warm_recover(const double *A, WarmRec &r)
 {
-    double n = A[0], nl = A[1];
-    r.lam = nl / n;
+    // two reciprocals (rcp64) instead of a division per quantity
+    const double n = A[0], nl = A[1];
+    const double in = rcp64(n), inl = rcp64(nl);
+    const double ilam = n * inl;  // 1 / lambda
+    r.lam = nl * in;
     if (DIM == 1) {
-        r.uz = A[2] / nl;
+        r.uz = A[2] * inl;
         r.ux = 0.0;
-        r.thzz = A[3] / r.lam;
+        r.thzz = A[3] * ilam;
         r.thxx = r.thyy = r.thxz = 0.0;
-        r.luz = A[2] / n;
+        r.luz = A[2] * in;
         r.lux = 0.0;
     } else {
-        r.uz = A[2] / nl;
-        r.ux = A[3] / nl;
-        r.thzz = A[4] / r.lam;
-        r.thxx = A[5] / r.lam;
-        r.thyy = A[6] / r.lam;
-        r.thxz = A[7] / r.lam;
-        r.luz = A[2] / n;
-        r.lux = A[3] / n;
+        r.uz = A[2] * inl;
+        r.ux = A[3] * inl;
+        r.thzz = A[4] * ilam;
+        r.thxx = A[5] * ilam;
+        r.thyy = A[6] * ilam;
+        r.thxz = A[7] * ilam;
+        r.luz = A[2] * in;
+        r.lux = A[3] * in;
     }
     r.th0z = r.ux * r.thxz + r.uz * r.thzz;
     r.th0x = r.ux * r.thxx + r.uz * r.thxz;

@@ -171,28 +171,49 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
         s_jx[rx][rz] = -n * ux;
     };
 
-    // ---- 2. ring nodes: pull, recover, keep only the LDS results
-    for (int t = tid; t < NRING; t += NT) {
-        int rz, rx;
-        if (t < RZ) { rz = t; rx = 0; }
-        else if (t < 2 * RZ) { rz = t - RZ; rx = RX - 1; }
-        else { const int u = t - 2 * RZ; rx = 1 + u / 2; rz = (u & 1) ? RZ - 1 : 0; }
-        CT sr[K][Q];
-        double Ar[K];
-        load(z0 - 1 + rz, x0 - 1 + rx, sr);
-        moments(sr, Ar);
-        double uzr, uxr;
-        recover_to_lds(Ar, rz, rx, uzr, uxr);
-    }
-
-    // ---- 3. own nodes: pull all of them, then recover; populations stay in registers
     const int lz = tid % TZ, lxb = tid / TZ;
     const int gz = z0 + lz;
     CT s[CPT][K][Q];
     double A[CPT][K];
     double uz[CPT], ux[CPT];
+    auto ring_node = [&](int t, int &rz, int &rx) {
+        if (t < RZ) { rz = t; rx = 0; }
+        else if (t < 2 * RZ) { rz = t - RZ; rx = RX - 1; }
+        else { const int u = t - 2 * RZ; rx = 1 + u / 2; rz = (u & 1) ? RZ - 1 : 0; }
+    };
+    if constexpr (CL == LEC && NRING <= NT) {
+        // ---- 2-3 (local equilibrium). Own nodes' loads first, then the ring
+        // node's (at most one per thread), so that both are in flight together;
+        // then the ring recovery and the own recoveries. Own populations stay
+        // in registers.
 #pragma unroll
-    for (int r = 0; r < CPT; ++r) load(gz, x0 + lxb + r * XS, s[r]);
+        for (int r = 0; r < CPT; ++r) load(gz, x0 + lxb + r * XS, s[r]);
+        int rz = 0, rx = 0;
+        double Ar[K];
+        if (tid < NRING) {
+            ring_node(tid, rz, rx);
+            CT sr[K][Q];
+            load(z0 - 1 + rz, x0 - 1 + rx, sr);
+            moments(sr, Ar);
+            double uzr, uxr;
+            recover_to_lds(Ar, rz, rx, uzr, uxr);
+        }
+    } else {
+        // ---- 2. ring nodes: pull, recover, keep only the LDS results
+        for (int t = tid; t < NRING; t += NT) {
+            int rz, rx;
+            ring_node(t, rz, rx);
+            CT sr[K][Q];
+            double Ar[K];
+            load(z0 - 1 + rz, x0 - 1 + rx, sr);
+            moments(sr, Ar);
+            double uzr, uxr;
+            recover_to_lds(Ar, rz, rx, uzr, uxr);
+        }
+        // ---- 3. own nodes: pull all of them; populations stay in registers
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) load(gz, x0 + lxb + r * XS, s[r]);
+    }
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
         moments(s[r], A[r]);

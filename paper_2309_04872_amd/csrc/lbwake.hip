@@ -24,7 +24,7 @@ namespace {
 #define LBW_TZ2 64
 #endif
 #ifndef LBW_TX2
-#define LBW_TX2 8
+#define LBW_TX2 16
 #endif
 #ifndef LBW_CPT2
 #define LBW_CPT2 1
