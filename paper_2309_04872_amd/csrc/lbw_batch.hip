@@ -137,6 +137,18 @@ __device__ __forceinline__ void step_pass(const BInst &P, const double *src, dou
     Node1<CL> nd[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) pull_node<CL>(P, src, base - 1 + tid + j * T, do_pull, nd[j]);
+    // the own nodes' E_z and lagged values are loaded with the populations, so
+    // that one memory round trip per pass serves them all
+    double ezv[CPT], lgv[CPT][3];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int slot = tid + j * T, gz = base - 1 + slot;
+        const bool own = slot >= 1 && slot <= W && gz < nz;
+        ezv[j] = own ? ez[gz] : 0.0;
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+            lgv[j][g] = (CL == WARMC && own && !lag_init) ? lag[(size_t)g * nzp + gz] : 0.0;
+    }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) recover_node<CL, T, CPT>(P, nd[j], sh, tid + j * T);
     __syncthreads();
@@ -148,7 +160,7 @@ __device__ __forceinline__ void step_pass(const BInst &P, const double *src, dou
         if (slot < 1 || slot > W || gz >= nz) continue;
         Node1<CL> &v = nd[j];
         const double n = v.A[0], uz = v.uz;
-        double Ez = ez[gz];
+        double Ez = ezv[j];
         if (do_maxwell) {
             const double jb = driver_density<1>(P.drv, gz * P.delta, 0.0, (step - 0.5) * dt);
             Ez = Ez + dt * (n * uz + jb);
@@ -167,7 +179,7 @@ __device__ __forceinline__ void step_pass(const BInst &P, const double *src, dou
             if (lag_init) {
                 l00 = th00; l0z = th0z; lluz = luz;
             } else {
-                l00 = lag[0 * nzp + gz]; l0z = lag[1 * nzp + gz]; lluz = lag[2 * nzp + gz];
+                l00 = lgv[j][0]; l0z = lgv[j][1]; lluz = lgv[j][2];
             }
             lag[0 * nzp + gz] = th00; lag[1 * nzp + gz] = th0z; lag[2 * nzp + gz] = luz;
             const double idt = 1.0 / dt;

@@ -214,6 +214,19 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 #pragma unroll
         for (int r = 0; r < CPT; ++r) load(gz, x0 + lxb + r * XS, s[r]);
     }
+    // warm closure: the own nodes' lagged values travel with the populations
+    // (one memory round trip for both)
+    double lagv[CPT][CL == WARMC ? NLAG2 : 1];
+    if constexpr (CL == WARMC) {
+#pragma unroll
+        for (int r = 0; r < CPT; ++r) {
+            const int gx = x0 + lxb + r * XS;
+            const bool own = gz < nz && gx < nx && !a.lag_init;
+            const size_t c = (size_t)gx * nz + gz;
+#pragma unroll
+            for (int g = 0; g < NLAG2; ++g) lagv[r][g] = own ? a.lag[g * nc + c] : 0.0;
+        }
+    }
 #pragma unroll
     for (int r = 0; r < CPT; ++r) {
         moments(s[r], A[r]);
@@ -319,8 +332,8 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
                 if (a.lag_init) {
                     l00 = th00; l0z = th0z; l0x = th0x; lluz = luz; llux = lux;
                 } else {
-                    l00 = a.lag[0 * nc + c]; l0z = a.lag[1 * nc + c]; l0x = a.lag[2 * nc + c];
-                    lluz = a.lag[3 * nc + c]; llux = a.lag[4 * nc + c];
+                    l00 = lagv[r][0]; l0z = lagv[r][1]; l0x = lagv[r][2];
+                    lluz = lagv[r][3]; llux = lagv[r][4];
                 }
                 a.lag[0 * nc + c] = th00; a.lag[1 * nc + c] = th0z; a.lag[2 * nc + c] = th0x;
                 a.lag[3 * nc + c] = luz; a.lag[4 * nc + c] = lux;
