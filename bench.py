@@ -83,6 +83,9 @@ def batch_bytes_per_step(insts):
     return sum(d["nz"] * bytes_per_lu(1, d["closure"], "fp64") for d in insts)
 
 
+BATCH_TRAFFIC_PER_STEP = 228.3e6
+
+
 def cpu_baseline_batch(insts, budget_s=12.0):
     """The CPU oracle on a bounded sample of the scan: its first instances in
     turn (alternating closures), 256 steps each, until the budget is spent."""
@@ -136,6 +139,10 @@ def bench_batch(args):
     k_ms = b.last_ms()  # HIP events on the batch's stream around the one launch
     bad = b.nonfinite()
     bps = batch_bytes_per_step(insts)
+    # HBM-side bytes per step measured with rocprofv3 (FETCH_SIZE, WRITE_SIZE,
+    # calibrated by a 1 GiB copy) for this kernel; the summary is in
+    # profiles/k_batch1d_batch1d_scan.md
+    traffic_per_step = BATCH_TRAFFIC_PER_STEP
     achieved = bps * steps / (k_ms / 1e3) / 1e9
     line = {
         "metric": "MLUPS (LB+field)",
@@ -159,7 +166,7 @@ def bench_batch(args):
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch1d",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_per_step * steps, "kernel": "k_batch1d",
             "kernel_avg_us": k_ms * 1e3, "bytes_per_step": bps, "launches": 1,
         },
         "wall_s": wall,

@@ -232,16 +232,19 @@ lbw_status lbw_adjoint_init_fields(lbw_sim *sim, const double *adj, double *grad
  * recoveries and forces, Sec. 5 field update and driver); the instances only
  * share the launch. lbw_batch_step runs all requested steps of every
  * instance inside one persistent kernel launch: one workgroup owns one
- * instance for the whole launch and separates consecutive steps with a
- * workgroup barrier, so no instance ever waits on another and the launch
- * needs no co-residency. Workgroups take instances longest first.
+ * instance for the whole launch and advances it in passes separated by
+ * workgroup barriers (two steps per pass after the first step, the state
+ * read and written once per two steps), so no instance ever waits on another
+ * and the launch needs no co-residency. Workgroups take instances longest
+ * first.
  *
  * The workspace is caller-owned device memory (256-byte aligned) of at least
  * lbw_batch_workspace_bytes(); the library allocates no device memory. It
  * holds, per instance, two population buffers (K x 3 planes of the padded
- * length, K = 2 for LEC and 4 for WARMC), E_z, the warm closure's three
- * lagged values, a snapshot of the state used by the autotuner, and the
- * instance's parameters, step counter and non-finite count.
+ * length, K = 2 for LEC and 4 for WARMC), two E_z buffers, two sets of the
+ * warm closure's three lagged values, a snapshot of the state used by the
+ * autotuner, and the instance's parameters, step counter and non-finite
+ * count.
  * ------------------------------------------------------------------------- */
 typedef struct {
     int nz;            /* nodes, >= 4 */

@@ -50,7 +50,8 @@ struct BState {
     int cur;        // population buffer holding the canonical f^n
     int lag_valid;  // warm closure lagged values exist
     int nonfinite;  // non-finite nodes at the end of the last launch
-    int pad[3];
+    int ecur;       // E_z / lagged-value buffer holding the current values
+    int pad[2];
 };
 
 struct BatchArgs {
@@ -66,6 +67,7 @@ struct BatchArgs {
 // pass (its nodes plus one ring node on each side).
 template <int T, int CPT> struct Lds {
     double g[3][T * CPT];
+    double xc[4][2][T * CPT];  // two-step pass: post-collision +z / -z populations
     int bad;
 };
 
@@ -118,6 +120,39 @@ __device__ __forceinline__ void recover_node(const BInst &P, Node1<CL> &nd, Lds<
     }
 }
 
+// Forcing (LEC: eq. lb-ade-lec-comps-F; WARMC: eq. lb-ade-warmc-comps-F, 1D,
+// time derivatives against the lagged values) and BGK collision with source
+// of one node whose E_z is already updated; rp / rm are the LDS slots of its
+// +z / -z neighbours. lag_out receives the values lagged for the next step.
+template <int CL, int T, int CPT>
+__device__ __forceinline__ void force_collide(const BInst &P, Node1<CL> &v, double Ez, const double *lag_in,
+                                              bool lag_init, double *lag_out, const Lds<T, CPT> &sh, int rp,
+                                              int rm)
+{
+    constexpr int K = NScal<1, CL>::K;
+    const double n = v.A[0], uz = v.uz, dt = P.dt;
+    auto Dz = [&](int g) { return (sh.g[g][rp] - sh.g[g][rm]) * P.inv2d; };
+    double F[K];
+    if constexpr (CL == LEC) {
+        F[0] = 0.0;
+        F[1] = -P.mu * Dz(0) - n * Ez;
+    } else {
+        const double th0z = v.w.th0z, thzz = v.w.thzz, luz = v.w.luz, th00 = v.w.th00;
+        const double l00 = lag_init ? th00 : lag_in[0], l0z = lag_init ? th0z : lag_in[1];
+        const double lluz = lag_init ? luz : lag_in[2];
+        lag_out[0] = th00;
+        lag_out[1] = th0z;
+        lag_out[2] = luz;
+        const double idt = 1.0 / dt;
+        F[0] = 0.0;
+        F[1] = -(th00 - l00) * idt - Dz(0) - n * (Ez * uz);
+        F[2] = -(th0z - l0z) * idt - Dz(1) - n * Ez;
+        F[3] = -2.0 * th0z * ((luz - lluz) * idt) - 2.0 * thzz * Dz(2) - 2.0 * (Ez * th0z);
+    }
+    const double zero[K] = {};
+    collide_all<1, K, double>(v.s, v.A, zero, F, uz, 0.0, P.lam, P.omega, dt);
+}
+
 // Nodes a pass owns: each of the T*CPT slots recovers one node (slot r holds
 // node base - 1 + r), the first and last slots being the ring that the
 // forces' central differences need; the slots in between collide.
@@ -168,32 +203,117 @@ __device__ __forceinline__ void step_pass(const BInst &P, const double *src, dou
         ez[gz] = Ez;
         const int rp = map_node(gz + 1, nz, P.bc) - (base - 1);
         const int rm = map_node(gz - 1, nz, P.bc) - (base - 1);
-        auto Dz = [&](int g) { return (sh.g[g][rp] - sh.g[g][rm]) * P.inv2d; };
-        double F[K];
-        if constexpr (CL == LEC) {
-            F[0] = 0.0;
-            F[1] = -P.mu * Dz(0) - n * Ez;
-        } else {
-            const double th0z = v.w.th0z, thzz = v.w.thzz, luz = v.w.luz, th00 = v.w.th00;
-            double l00, l0z, lluz;
-            if (lag_init) {
-                l00 = th00; l0z = th0z; lluz = luz;
-            } else {
-                l00 = lgv[j][0]; l0z = lgv[j][1]; lluz = lgv[j][2];
-            }
-            lag[0 * nzp + gz] = th00; lag[1 * nzp + gz] = th0z; lag[2 * nzp + gz] = luz;
-            const double idt = 1.0 / dt;
-            F[0] = 0.0;
-            F[1] = -(th00 - l00) * idt - Dz(0) - n * (Ez * uz);
-            F[2] = -(th0z - l0z) * idt - Dz(1) - n * Ez;
-            F[3] = -2.0 * th0z * ((luz - lluz) * idt) - 2.0 * thzz * Dz(2) - 2.0 * (Ez * th0z);
+        double lnew[3];
+        force_collide<CL, T, CPT>(P, v, Ez, lgv[j], lag_init, lnew, sh, rp, rm);
+        if constexpr (CL == WARMC) {
+#pragma unroll
+            for (int g = 0; g < 3; ++g) lag[(size_t)g * nzp + gz] = lnew[g];
         }
-        const double zero[K] = {};
-        collide_all<1, K, double>(v.s, v.A, zero, F, uz, 0.0, P.lam, P.omega, dt);
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + gz] = v.s[k][q];
+    }
+    __syncthreads();  // the next pass reuses the LDS slots
+}
+
+// Two steps in one pass (temporal blocking). Slot r of the T*CPT slots holds
+// node fix(base - 3 + r) (the copy or wrap rule of the boundary): step t runs
+// on slots [1, NS - 1), its post-collision +z / -z populations go through LDS,
+// and step t + 1 runs on the own slots [3, NS - 3), i.e. nodes
+// [base, base + NS - 6). Populations, E_z and lagged values are read once and
+// written once per two steps; E_z and the lagged values are read from one
+// buffer and written to the other, because the ring slots read values that a
+// neighbouring pass of the same sweep updates.
+template <int T, int CPT> constexpr int pass2_width() { return T * CPT - 6; }
+
+template <int CL, int T, int CPT>
+__device__ __forceinline__ void step_pass2(const BInst &P, const double *src, double *dst, const double *ez_in,
+                                           double *ez_out, const double *lag_in, double *lag_out, int base,
+                                           long step, Lds<T, CPT> &sh)
+{
+    constexpr int K = NScal<1, CL>::K;
+    constexpr int NS = T * CPT;
+    const int tid = threadIdx.x;
+    const int nz = P.nz, bc = P.bc;
+    const size_t nzp = (size_t)P.nzp;
+    const double dt = P.dt;
+    const int off = base - 3;  // node of slot 0 before the boundary rule
+    // LDS slot of the node next to slot r's node (r's node is fix(off + r))
+    auto nb = [&](int r, int d) {
+        return bc == BC_PERIODIC ? r + d : map_node(fix_node(off + r, nz, bc) + d, nz, bc) - off;
+    };
+    // ---- step t on every slot: pull, E_z, lagged values, recovery into LDS
+    Node1<CL> nd[CPT];
+    double ezv[CPT], lgv[CPT][3];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int z = fix_node(off + tid + j * T, nz, bc);
+        pull_node<CL>(P, src, z, true, nd[j]);
+        ezv[j] = ez_in[z];
+#pragma unroll
+        for (int g = 0; g < 3; ++g) lgv[j][g] = CL == WARMC ? lag_in[(size_t)g * nzp + z] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) recover_node<CL, T, CPT>(P, nd[j], sh, tid + j * T);
+    __syncthreads();
+    double rest[CPT][K], lagt[CPT][3];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int r = tid + j * T;
+        if (r < 1 || r >= NS - 1) continue;
+        const int z = fix_node(off + r, nz, bc);
+        Node1<CL> &v = nd[j];
+        const double jb = driver_density<1>(P.drv, z * P.delta, 0.0, (step - 0.5) * dt);
+        ezv[j] = ezv[j] + dt * (v.A[0] * v.uz + jb);
+        force_collide<CL, T, CPT>(P, v, ezv[j], lgv[j], false, lagt[j], sh, nb(r, 1), nb(r, -1));
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            rest[j][k] = v.s[k][0];
+            sh.xc[k][0][r] = v.s[k][1];
+            sh.xc[k][1][r] = v.s[k][2];
+        }
+    }
+    __syncthreads();  // movers in LDS; every step-t value of g has been read
+    // ---- step t + 1: pull from LDS on slots [2, NS - 2), recovery into LDS
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int r = tid + j * T;
+        if (r < 2 || r >= NS - 2) continue;
+        Node1<CL> &v = nd[j];
+        const int rm = nb(r, -1), rp = nb(r, 1);  // sources of +z and -z movers
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v.s[k][0] = rest[j][k];
+            v.s[k][1] = sh.xc[k][0][rm];
+            v.s[k][2] = sh.xc[k][1][rp];
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc += v.s[k][q];
+            v.A[k] = 0.0 + acc;
+        }
+        recover_node<CL, T, CPT>(P, v, sh, r);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int r = tid + j * T;
+        const int z = off + r;
+        if (r < 3 || r >= NS - 3 || z >= nz) continue;
+        Node1<CL> &v = nd[j];
+        const double jb = driver_density<1>(P.drv, z * P.delta, 0.0, (step + 0.5) * dt);
+        const double Ez = ezv[j] + dt * (v.A[0] * v.uz + jb);
+        double lnew[3];
+        force_collide<CL, T, CPT>(P, v, Ez, lagt[j], false, lnew, sh, nb(r, 1), nb(r, -1));
+        ez_out[z] = Ez;
+        if constexpr (CL == WARMC) {
+#pragma unroll
+            for (int g = 0; g < 3; ++g) lag_out[(size_t)g * nzp + z] = lnew[g];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + z] = v.s[k][q];
     }
     __syncthreads();  // the next pass reuses the LDS slots
 }
@@ -238,32 +358,51 @@ template <int CL, int T, int CPT>
 __device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds<T, CPT> &sh)
 {
     constexpr int W = pass_width<T, CPT>();
+    constexpr int W2 = pass2_width<T, CPT>();
     constexpr int WF = T * CPT;  // finish passes own every slot
     const int nsteps = a.nsteps;
-    int cur = st->cur;
+    int cur = st->cur, ec = st->ecur;
     const long step0 = st->step;
     const bool lag_init = st->lag_valid == 0;
+    const size_t nzp = (size_t)P.nzp;
     double *pop[2] = {a.pop0 + P.pop, a.pop1 + P.pop};
-    double *ez = a.ez + P.fld;
-    double *lag = CL == WARMC ? a.lag + P.lag : nullptr;
-    for (int s = 0; s < nsteps; ++s) {
-        const bool from_canonical = s == 0;
+    double *ez[2] = {a.ez + P.fld, a.ez + P.fld + nzp};
+    double *lag[2] = {a.lag + P.lag, a.lag + P.lag + (CL == WARMC ? NLAG1 * nzp : 0)};
+    // schedule: the first step from the canonical state, then pairs of steps
+    // in two-step passes, then a last single step if one is left. Every pass
+    // ends on a barrier, so each step's stores are visible to the whole
+    // workgroup before the next step reads its neighbours.
+    long s = 0;
+    if (nsteps > 0) {
         for (int base = 0; base < P.nz; base += W)
-            step_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez, lag, base, !from_canonical,
-                                  !from_canonical, from_canonical && lag_init, step0 + s, sh);
+            step_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez[ec], lag[ec], base, false, false, lag_init,
+                                  step0, sh);
         cur ^= 1;
-        // step_pass ends on a barrier: every store of this step is visible to
-        // the whole workgroup before the next step reads its neighbours
+        s = 1;
+    }
+    for (; s + 2 <= nsteps; s += 2) {
+        for (int base = 0; base < P.nz; base += W2)
+            step_pass2<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez[ec], ez[ec ^ 1], lag[ec], lag[ec ^ 1], base,
+                                   step0 + s, sh);
+        cur ^= 1;
+        ec ^= 1;
+    }
+    if (s < nsteps) {
+        for (int base = 0; base < P.nz; base += W)
+            step_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez[ec], lag[ec], base, true, true, false, step0 + s,
+                                  sh);
+        cur ^= 1;
     }
     if (threadIdx.x == 0) sh.bad = 0;
     __syncthreads();
     int bad = 0;
     for (int base = 0; base < P.nz; base += WF)
-        bad += finish_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez, base, step0 + nsteps);
+        bad += finish_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez[ec], base, step0 + nsteps);
     if (bad) atomicAdd(&sh.bad, bad);
     __syncthreads();
     if (threadIdx.x == 0) {
         st->cur = cur ^ 1;
+        st->ecur = ec;
         st->step = step0 + nsteps;
         st->lag_valid = 1;
         st->nonfinite = sh.bad;
@@ -331,8 +470,8 @@ BLayout make_blayout(const lbw_instance_desc *d, int n)
     for (int i = 0; i < n; ++i) {
         const size_t np = padded(d[i].nz);
         pe += (size_t)nscal1(d[i].closure) * 3 * np;
-        fe += np;
-        if (d[i].closure == LBW_WARMC) le += NLAG1 * np;
+        fe += 2 * np;
+        if (d[i].closure == LBW_WARMC) le += 2 * NLAG1 * np;
     }
     L.pop_elems = pe;
     L.fld_elems = fe;
@@ -370,7 +509,8 @@ struct lbw_batch {
     int cfg;
     bool initialized;
     long step;
-    int cur;  // host mirror of every instance's buffer parity
+    int cur;   // host mirror of every instance's population buffer parity
+    int ecur;  // host mirror of the E_z / lagged-value buffer index
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
     std::string err;
@@ -430,8 +570,8 @@ static StepArgs instance_args(lbw_batch *b, int i)
     a.step = b->step;
     a.src = (double *)(b->ws + b->L.pop[b->cur]) + P.pop;
     a.dst = nullptr;
-    a.ez_in = (const double *)(b->ws + b->L.ez) + P.fld;
-    a.ez_out = (double *)(b->ws + b->L.ez) + P.fld;
+    a.ez_in = (const double *)(b->ws + b->L.ez) + P.fld + (size_t)b->ecur * P.nzp;
+    a.ez_out = (double *)(b->ws + b->L.ez) + P.fld + (size_t)b->ecur * P.nzp;
     return a;
 }
 
@@ -469,6 +609,7 @@ lbw_status lbw_batch_create(const lbw_instance_desc *d, int n, void *ws, size_t 
     b->initialized = false;
     b->step = 0;
     b->cur = 0;
+    b->ecur = 0;
     size_t pe = 0, fe = 0, le = 0;
     for (int i = 0; i < n; ++i) {
         const lbw_instance_desc &q = d[i];
@@ -483,8 +624,8 @@ lbw_status lbw_batch_create(const lbw_instance_desc *d, int n, void *ws, size_t 
         P.fld = fe;
         P.lag = le;
         pe += (size_t)P.K * 3 * P.nzp;
-        fe += P.nzp;
-        if (q.closure == LBW_WARMC) le += NLAG1 * (size_t)P.nzp;
+        fe += 2 * (size_t)P.nzp;  // two E_z buffers
+        if (q.closure == LBW_WARMC) le += 2 * NLAG1 * (size_t)P.nzp;
         P.delta = q.delta;
         P.dt = q.dt;
         P.inv2d = 1.0 / (2.0 * q.delta);
@@ -551,8 +692,9 @@ lbw_status lbw_batch_init(lbw_batch *b, const double *n_init)
     b->initialized = false;
     b->step = 0;
     b->cur = 0;
+    b->ecur = 0;
     std::vector<BState> st(n);
-    for (auto &x : st) x = BState{0, 0, 0, 0, {0, 0, 0}};
+    for (auto &x : st) x = BState{0, 0, 0, 0, 0, {0, 0}};
     BHIPCHK(b, hipMemcpyAsync(b->ws + b->L.st, st.data(), n * sizeof(BState), hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipMemsetAsync(b->ws + b->L.ez, 0, b->L.fld_elems * 8, b->stream));
     BHIPCHK(b, hipMemsetAsync(b->ws + b->L.lag, 0, b->L.lag_elems * 8 + 8, b->stream));
@@ -650,8 +792,14 @@ lbw_status lbw_batch_step(lbw_batch *b, int nsteps, int use_graph)
     if (rc != LBW_OK) return rc;
     BHIPCHK(b, hipEventRecord(b->ev[1], b->stream));
     b->ev_recorded = true;
+    // the launch's schedule (run_instance): one single step, (nsteps - 1) / 2
+    // two-step sweeps, one more single step if nsteps - 1 is odd, the finish;
+    // each sweep and the finish swap the population buffers, each two-step
+    // sweep swaps the E_z / lagged-value buffers
+    const int pairs = (nsteps - 1) / 2, single_tail = (nsteps - 1) % 2;
     b->step += nsteps;
-    b->cur ^= (nsteps + 1) & 1;
+    b->cur ^= (1 + pairs + single_tail + 1) & 1;
+    b->ecur ^= pairs & 1;
     return LBW_OK;
 }
 
@@ -708,7 +856,7 @@ lbw_status lbw_batch_autotune(lbw_batch *b, int probe_steps, int *threads, int *
     if (!b->initialized) return bfail(b, LBW_ERR_STATE, "lbw_batch_init first");
     if (probe_steps < 1) return bfail(b, LBW_ERR_ARG, "probe_steps must be >= 1");
     const long step0 = b->step;
-    const int cur0 = b->cur;
+    const int cur0 = b->cur, ecur0 = b->ecur;
     lbw_status rc = snapshot(b, true);
     if (rc != LBW_OK) return rc;
     double best = 1e300;
@@ -720,6 +868,7 @@ lbw_status lbw_batch_autotune(lbw_batch *b, int probe_steps, int *threads, int *
             rc = snapshot(b, false);
             b->step = step0;
             b->cur = cur0;
+            b->ecur = ecur0;
             if (rc == LBW_OK) rc = lbw_batch_step(b, probe_steps, 0);
             if (rc != LBW_OK) break;
         }
@@ -733,6 +882,7 @@ lbw_status lbw_batch_autotune(lbw_batch *b, int probe_steps, int *threads, int *
     }
     b->step = step0;
     b->cur = cur0;
+    b->ecur = ecur0;
     lbw_status rc2 = snapshot(b, false);
     if (rc == LBW_OK) rc = rc2;
     BHIPCHK(b, hipStreamSynchronize(b->stream));
