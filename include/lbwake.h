@@ -201,8 +201,8 @@ lbw_status lbw_load_state_device(lbw_sim *sim, const void *device_src, long step
  * Sec. 5): the transposed Jacobian of one step of lbw_step, and the
  * derivatives of the driver's slice weights (per-slice current profile) in
  * the bunch current and in the initial fields. 2D, LBW_LEC, any storage
- * (the adjoint itself is FP64); LBW_ERR_UNSUPPORTED otherwise, LBW_ERR_STATE
- * when the driver has no slices.
+ * (the adjoint itself is FP64), at most 1024 slices; LBW_ERR_UNSUPPORTED
+ * otherwise, LBW_ERR_STATE when the driver has no slices.
  *
  * adj (device, FP64, caller-owned) holds the adjoint of a canonical state:
  * K*Q population planes in the population order, then E_z, E_x, B_y, each

@@ -27,7 +27,10 @@ struct AdjArgs {
     const double *ez, *ex, *by;           // E^n, B^{n-1/2} (Yee arrays)
     double *lf, *lez, *lex, *lby;         // adjoint of the state, updated in place
     double *s_byt, *s_fs, *s_fz, *s_fx;   // scratch: adjoint of B', of f*, of F
-    double *s_enz, *s_enx, *s_bny, *s_bht, *s_col;
+    double *s_enz, *s_enx, *s_bny, *s_bht;
+    double *s_ab;                         // adjoint of A at n+1 (3 planes), added in the stream gather
+    double *s_bhf;                        // forward Bh = B^{n-1/2} - dt/2 curl E^n at every slot
+    double *s_x;                          // adjoint(B') + adjoint(Bh)
     const double *aref;
     double *grad;                         // d loss / d slice weight, accumulated
     int nz, nx, ncell, bcz, bcx;
@@ -145,8 +148,35 @@ __device__ __forceinline__ void moments3(const void *f, const AdjArgs &a, size_t
     }
 }
 
+// Forward node fields at node (j, i) from E^n and B^{n-1/2} (S3).
+struct NodeF {
+    double ez, ex, by;
+};
+
+__device__ __forceinline__ double curl_e_at(const AdjArgs &a, int j, int i)
+{
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    auto EZ = [&](int jj, int ii) { return a.ez[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    auto EX = [&](int jj, int ii) { return a.ex[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
+    return ((EX(j, i + 1) - EX(j, i)) - (EZ(j + 1, i) - EZ(j, i))) / a.delta;
+}
+
+__device__ __forceinline__ NodeF node_fields_at(const AdjArgs &a, int j, int i)
+{
+    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+    auto EZ = [&](int jj, int ii) { return a.ez[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    auto EX = [&](int jj, int ii) { return a.ex[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
+    auto BH = [&](int jj, int ii) { return a.s_bhf[(size_t)fix_stag(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
+    NodeF f;
+    f.ez = 0.5 * (EZ(j, i - 1) + EZ(j, i));
+    f.ex = 0.5 * (EX(j - 1, i) + EX(j, i));
+    f.by = 0.25 * (BH(j, i) + BH(j, i - 1) + BH(j - 1, i) + BH(j - 1, i - 1));
+    return f;
+}
+
 // (a) Reverse of S9 and S8 at every slot/node y: adjoint of B', the currents'
-// adjoint m'b, through the recovery at n+1 into the adjoint of f'.
+// adjoint m'b, through the recovery at n+1 into the adjoint of A' (every
+// population of the node gets it; the stream gather adds it).
 template <class ST>
 __global__ __launch_bounds__(256) void k_adj_maxwell(AdjArgs a)
 {
@@ -177,13 +207,14 @@ __global__ __launch_bounds__(256) void k_adj_maxwell(AdjArgs a)
     lec_recover_adj(J, A[0] * mzb, A[0] * mxb, 0.0, mzb * J.uz + mxb * J.ux, 1.0 + a.two_over_d, Ab);
     const size_t nc = (size_t)a.ncell;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int q = 0; q < 9; ++q) a.lf[(size_t)(k * 9 + q) * nc + y] += Ab[k];
+    for (int k = 0; k < 3; ++k) a.s_ab[(size_t)k * nc + y] = Ab[k];
+    // forward Bh at this slot, for the node fields of the collision kernel
+    a.s_bhf[y] = a.by[y] - 0.5 * dt * curl_e_at(a, jy, iy);
 }
 
 // (b) Reverse of S7 (streaming): adjoint of f* gathered from the nodes that
-// pulled from y; adjoint of the forcing F_k = dt sum_q w_q fs_b.
+// pulled from y (their adjoint of f' plus their adjoint of A'); adjoint of
+// the forcing F_k = dt sum_q w_q fs_b.
 __global__ __launch_bounds__(256) void k_adj_stream(AdjArgs a)
 {
     using L = Lattice<2>;
@@ -200,44 +231,19 @@ __global__ __launch_bounds__(256) void k_adj_stream(AdjArgs a)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double *lfq = a.lf + (size_t)(k * 9 + q) * nc;
+            const double *abk = a.s_ab + (size_t)k * nc;
             double acc = 0.0;
             for (int u = 0; u < nxc; ++u)
-                for (int v = 0; v < nzc; ++v) acc += lfq[(size_t)cx[u] * a.nz + cz[v]];
+                for (int v = 0; v < nzc; ++v) {
+                    const size_t c = (size_t)cx[u] * a.nz + cz[v];
+                    acc += lfq[c] + abk[c];
+                }
             a.s_fs[(size_t)(k * 9 + q) * nc + y] = acc;
             Fb[k] += L::w(q) * acc;
         }
     }
     a.s_fz[y] = a.dt * Fb[1];
     a.s_fx[y] = a.dt * Fb[2];
-}
-
-// Forward node fields at node (j, i) from E^n and B^{n-1/2} (S3).
-struct NodeF {
-    double ez, ex, by;
-};
-
-__device__ __forceinline__ double curl_e_at(const AdjArgs &a, int j, int i)
-{
-    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
-    auto EZ = [&](int jj, int ii) { return a.ez[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
-    auto EX = [&](int jj, int ii) { return a.ex[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
-    return ((EX(j, i + 1) - EX(j, i)) - (EZ(j + 1, i) - EZ(j, i))) / a.delta;
-}
-
-__device__ __forceinline__ NodeF node_fields_at(const AdjArgs &a, int j, int i)
-{
-    const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
-    auto EZ = [&](int jj, int ii) { return a.ez[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
-    auto EX = [&](int jj, int ii) { return a.ex[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
-    auto BH = [&](int jj, int ii) {
-        const int js = fix_stag(jj, nx, bx), is = fix_stag(ii, nz, bz);
-        return a.by[(size_t)js * nz + is] - 0.5 * a.dt * curl_e_at(a, js, is);
-    };
-    NodeF f;
-    f.ez = 0.5 * (EZ(j, i - 1) + EZ(j, i));
-    f.ex = 0.5 * (EX(j - 1, i) + EX(j, i));
-    f.by = 0.25 * (BH(j, i) + BH(j, i - 1) + BH(j - 1, i) + BH(j - 1, i - 1));
-    return f;
 }
 
 // (c) Reverse of S6, S5, S2, S1 at node y: collision, forcing (the gradient
@@ -322,10 +328,11 @@ __global__ __launch_bounds__(256) void k_adj_bh(AdjArgs a)
                  gather2(a.s_bny, jy, iy, -1, 0, true, true, nx, nz, bx, bz) +
                  gather2(a.s_bny, jy, iy, -1, -1, true, true, nx, nz, bx, bz));
     a.s_bht[y] = b;
+    a.s_x[y] = a.s_byt[y] + b;  // X: the adjoint both dt/2 curls of E^n see
 }
 
 // (d2) Adjoint of E^n (identity, node averages, and the two dt/2 curls of S3
-// and S9) and of B^{n-1/2}; s_col holds X = adjoint(B') + adjoint(Bh).
+// and S9, both taken of X = adjoint(B') + adjoint(Bh)) and of B^{n-1/2}.
 __global__ __launch_bounds__(256) void k_adj_fields(AdjArgs a)
 {
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
@@ -333,37 +340,38 @@ __global__ __launch_bounds__(256) void k_adj_fields(AdjArgs a)
     const int iy = y % a.nz, jy = y / a.nz;
     const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
     const double hdi = 0.5 * a.dt / a.delta;
-    const double *X = a.s_col;
+    auto gX = [&](int dx, int dz, bool sx, bool sz) { return gather2(a.s_x, jy, iy, dx, dz, sx, sz, nx, nz, bx, bz); };
     // E_z slot (x node, z staggered): read by En_z at (j, i + 1) as i - 1 and at
     // (j, i); by curlE at (j - 1, i) as j + 1 (minus) and at (j, i) (plus)
     double ez = a.lez[y];
     ez += 0.5 * (gather2(a.s_enz, jy, iy, 0, -1, false, true, nx, nz, bx, bz) +
                  gather2(a.s_enz, jy, iy, 0, 0, false, true, nx, nz, bx, bz));
-    ez -= hdi * (-gather2(X, jy, iy, 1, 0, false, true, nx, nz, bx, bz) +
-                 gather2(X, jy, iy, 0, 0, false, true, nx, nz, bx, bz));
+    ez -= hdi * (-gX(1, 0, false, true) + gX(0, 0, false, true));
     // E_x slot (x staggered, z node)
     double ex = a.lex[y];
     ex += 0.5 * (gather2(a.s_enx, jy, iy, -1, 0, true, false, nx, nz, bx, bz) +
                  gather2(a.s_enx, jy, iy, 0, 0, true, false, nx, nz, bx, bz));
-    ex -= hdi * (gather2(X, jy, iy, 0, 1, true, false, nx, nz, bx, bz) -
-                 gather2(X, jy, iy, 0, 0, true, false, nx, nz, bx, bz));
+    ex -= hdi * (gX(0, 1, true, false) - gX(0, 0, true, false));
     a.lez[y] = ez;
     a.lex[y] = ex;
     a.lby[y] = a.s_bht[y];
 }
 
-__global__ __launch_bounds__(256) void k_adj_sum_bx(AdjArgs a)
+
+// Slice of position (i + zoff) delta at time t (the forward's slice_weight
+// index rule), or -1 outside the slice span.
+__device__ __forceinline__ int slice_of(const Driver &d, double zeta)
 {
-    const int y = blockIdx.x * blockDim.x + threadIdx.x;
-    if (y >= a.ncell) return;
-    a.s_col[y] = a.s_byt[y] + a.s_bht[y];
+    if (!(zeta >= d.slice_zmin && zeta < d.slice_zmax)) return -1;
+    int k = (int)floor((zeta - d.slice_zmin) / (d.slice_zmax - d.slice_zmin) * d.nslices);
+    return k < 0 ? 0 : (k >= d.nslices ? d.nslices - 1 : k);
 }
 
 // Slice derivatives of the driver current: E'_z gains dt n_b at
 // ((i + 1/2) delta, x_j, t^{n+1/2}), n_b = alpha w_s exp(-e). One workgroup per
 // column of the bunch window [i0, i0 + gridDim.x) sums over x (tree
-// reduction, fixed order); then one thread per slice adds its columns in
-// order.
+// reduction, fixed order) into col[i], with the column's slice in
+// col[nz + i]; then one thread per slice adds its columns in order.
 __global__ __launch_bounds__(256) void k_adj_drv_cols(AdjArgs a, const double *lez, double t, double zoff, int i0,
                                                       double *col)
 {
@@ -384,12 +392,17 @@ __global__ __launch_bounds__(256) void k_adj_drv_cols(AdjArgs a, const double *l
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) col[i] = red[0];
+    if (threadIdx.x == 0) {
+        col[i] = red[0];
+        col[a.nz + i] = (double)slice_of(d, zeta);
+    }
 }
 
 // Initial fields: E_x(j, i) = g(zeta_e) tr(j), B_y(j, i) = g(zeta_b) tr(j) with
-// g = alpha w_s exp(-zeta^2 / 2 sigma_z^2); per column sum_j lambda tr(j).
-__global__ __launch_bounds__(256) void k_adj_init_cols(AdjArgs a, const double *lam, int i0, double *col)
+// g = alpha w_s exp(-zeta^2 / 2 sigma_z^2); col[i] = exp(-zeta^2 / 2 sigma_z^2)
+// sum_j lambda tr(j) and the column's slice in col[nz + i].
+__global__ __launch_bounds__(256) void k_adj_init_cols(AdjArgs a, const double *lam, double t, double zoff, int i0,
+                                                       double *col)
 {
     __shared__ double red[256];
     const int i = i0 + blockIdx.x;
@@ -406,28 +419,39 @@ __global__ __launch_bounds__(256) void k_adj_init_cols(AdjArgs a, const double *
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) col[i] = red[0];
+    if (threadIdx.x == 0) {
+        const double zeta = (i + zoff) * a.delta - d.z0 - t;
+        col[i] = red[0] * exp(-zeta * zeta * d.inv2sz2);
+        col[a.nz + i] = (double)slice_of(d, zeta);
+    }
 }
 
-// grad[s] += scale * alpha * sum over the window's columns i in slice s of
-// col[i] (times exp(-zeta^2 / (2 sigma_z^2)) when with_exp: the initial
-// fields, whose column sums hold only the x profile).
-__global__ void k_adj_slices(AdjArgs a, const double *col, double t, double zoff, int i0, int i1, double scale,
-                             int with_exp)
+// grad[s] += scale * alpha * sum of col[i] over the window's columns of slice
+// s; the window is staged through LDS in chunks of 256 columns.
+__global__ __launch_bounds__(256) void k_adj_slices(AdjArgs a, const double *col, int i0, int i1, double scale)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const Driver &d = a.drv;
-    if (s >= d.nslices) return;
-    double acc = 0.0;
-    for (int i = i0; i < i1; ++i) {
-        const double zeta = (i + zoff) * a.delta - d.z0 - t;
-        if (!(zeta >= d.slice_zmin && zeta < d.slice_zmax)) continue;
-        int k = (int)floor((zeta - d.slice_zmin) / (d.slice_zmax - d.slice_zmin) * d.nslices);
-        k = k < 0 ? 0 : (k >= d.nslices ? d.nslices - 1 : k);
-        if (k != s) continue;
-        acc += col[i] * (with_exp ? exp(-zeta * zeta * d.inv2sz2) : 1.0);
+    __shared__ double cv[256];
+    __shared__ int ck[256];
+    const int ns = a.drv.nslices;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // slices threadIdx.x + 256 m, m < 4
+    for (int c0 = i0; c0 < i1; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        cv[threadIdx.x] = i < i1 ? col[i] : 0.0;
+        ck[threadIdx.x] = i < i1 ? (int)col[a.nz + i] : -1;
+        __syncthreads();
+        const int n = i1 - c0 < 256 ? i1 - c0 : 256;
+        for (int m = 0; m < 4; ++m) {
+            const int s = threadIdx.x + 256 * m;
+            if (s >= ns) break;
+            for (int c = 0; c < n; ++c)
+                if (ck[c] == s) acc[m] += cv[c];
+        }
+        __syncthreads();
     }
-    a.grad[s] += scale * d.alpha * acc;
+    for (int m = 0; m < 4; ++m) {
+        const int s = threadIdx.x + 256 * m;
+        if (s < ns) a.grad[s] += scale * a.drv.alpha * acc[m];
+    }
 }
 
 }  // namespace lbw

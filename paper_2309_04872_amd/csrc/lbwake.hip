@@ -774,7 +774,7 @@ DevStateLayout dev_state_layout(const lbw_sim *s)
     d.total = off;
     return d;
 }
-constexpr int ADJ_SCRATCH_PLANES = 8;  // B' adjoint, F_z, F_x, En_z, En_x, Bn_y, Bh, sum
+constexpr int ADJ_SCRATCH_PLANES = 12;  // B', F_z, F_x, En_z, En_x, Bn_y, Bh adjoints; A' adjoint (3); forward Bh; X
 }  // namespace
 
 size_t lbw_state_device_bytes(const lbw_sim *s) { return s ? dev_state_layout(s).total : 0; }
@@ -830,7 +830,7 @@ size_t lbw_adjoint_workspace_bytes(const lbw_sim *s)
 {
     if (!s) return 0;
     const size_t nc = (size_t)s->g.nz * s->g.nx;
-    return ((size_t)s->L.K * s->L.Q + ADJ_SCRATCH_PLANES) * align_up(nc * 8) + align_up((size_t)s->g.nz * 8);
+    return ((size_t)s->L.K * s->L.Q + ADJ_SCRATCH_PLANES) * align_up(nc * 8) + align_up((size_t)s->g.nz * 16);
 }
 
 static lbw_status adj_args(lbw_sim *s, double *adj, double *grad, void *scratch, AdjArgs &a)
@@ -840,6 +840,7 @@ static lbw_status adj_args(lbw_sim *s, double *adj, double *grad, void *scratch,
     if (s->g.dims != 2 || s->g.closure != LBW_LEC)
         return fail(s, LBW_ERR_UNSUPPORTED, "the adjoint covers the 2D local-equilibrium closure");
     if (s->drv.nslices <= 0) return fail(s, LBW_ERR_STATE, "the driver has no slices to differentiate");
+    if (s->drv.nslices > 1024) return fail(s, LBW_ERR_UNSUPPORTED, "the adjoint handles at most 1024 slices");
     if (((uintptr_t)scratch % ALIGN) != 0) return fail(s, LBW_ERR_ARG, "scratch must be 256-byte aligned");
     const size_t nc = (size_t)s->g.nz * s->g.nx;
     a = AdjArgs{};
@@ -853,7 +854,9 @@ static lbw_status adj_args(lbw_sim *s, double *adj, double *grad, void *scratch,
     double *pls[ADJ_SCRATCH_PLANES];
     for (int k = 0; k < ADJ_SCRATCH_PLANES; ++k) { pls[k] = (double *)p; p += pl; }
     a.s_byt = pls[0]; a.s_fz = pls[1]; a.s_fx = pls[2]; a.s_enz = pls[3]; a.s_enx = pls[4];
-    a.s_bny = pls[5]; a.s_bht = pls[6]; a.s_col = pls[7];
+    a.s_bny = pls[5]; a.s_bht = pls[6]; a.s_ab = pls[7]; a.s_bhf = pls[10]; a.s_x = pls[11];
+    // s_ab spans planes 7, 8, 9 (one per advected scalar, indexed k * ncell
+    // from plane 7: within the three planes since a plane is >= ncell values)
     a.aref = (const double *)(s->ws + s->L.aref);
     a.grad = grad;
     a.nz = s->g.nz; a.nx = s->g.nx; a.ncell = (int)nc; a.bcz = s->g.bc_z; a.bcx = s->g.bc_x;
@@ -882,7 +885,6 @@ template <class ST>
 static void adj_step_launch(const AdjArgs &a, double *col, hipStream_t st)
 {
     const int nb = (a.ncell + 255) / 256;
-    const int nbs = (a.drv.nslices + 63) / 64;
     hipLaunchKernelGGL((k_adj_maxwell<ST>), dim3(nb), dim3(256), 0, st, a);
     // slice derivatives read the adjoint of E^{n+1} before it is overwritten
     const double th = (a.step + 0.5) * a.dt;
@@ -891,13 +893,11 @@ static void adj_step_launch(const AdjArgs &a, double *col, hipStream_t st)
     if (i1 > i0) {
         hipLaunchKernelGGL(k_adj_drv_cols, dim3(i1 - i0), dim3(256), 0, st, a, (const double *)a.lez, th, 0.5, i0,
                            col);
-        hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, st, a, (const double *)col, th, 0.5, i0, i1, a.dt,
-                           0);
+        hipLaunchKernelGGL(k_adj_slices, dim3(1), dim3(256), 0, st, a, (const double *)col, i0, i1, a.dt);
     }
     hipLaunchKernelGGL(k_adj_stream, dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_adj_collide<ST>), dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_adj_bh, dim3(nb), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_adj_sum_bx, dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_adj_fields, dim3(nb), dim3(256), 0, st, a);
 }
 }  // extern "C++"
@@ -934,22 +934,19 @@ lbw_status lbw_adjoint_init_fields(lbw_sim *s, const double *adj, double *grad, 
     if (rc != LBW_OK) return rc;
     double *col = (double *)((char *)scratch + ((size_t)s->L.K * s->L.Q + ADJ_SCRATCH_PLANES) *
                                                    align_up((size_t)a.ncell * 8));
-    const int nbs = (a.drv.nslices + 63) / 64;
     // E_x(0) at zeta = i delta - z0; B_y(-dt/2) at zeta = (i + 1/2) delta - z0 + dt/2
     int i0, i1;
     slice_window(a, 0.0, 0.0, i0, i1);
     if (i1 > i0) {
-        hipLaunchKernelGGL(k_adj_init_cols, dim3(i1 - i0), dim3(256), 0, s->stream, a, (const double *)a.lex, i0,
-                           col);
-        hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, s->stream, a, (const double *)col, 0.0, 0.0, i0,
-                           i1, 1.0, 1);
+        hipLaunchKernelGGL(k_adj_init_cols, dim3(i1 - i0), dim3(256), 0, s->stream, a, (const double *)a.lex, 0.0,
+                           0.0, i0, col);
+        hipLaunchKernelGGL(k_adj_slices, dim3(1), dim3(256), 0, s->stream, a, (const double *)col, i0, i1, 1.0);
     }
     slice_window(a, -0.5 * a.dt, 0.5, i0, i1);
     if (i1 > i0) {
-        hipLaunchKernelGGL(k_adj_init_cols, dim3(i1 - i0), dim3(256), 0, s->stream, a, (const double *)a.lby, i0,
-                           col);
-        hipLaunchKernelGGL(k_adj_slices, dim3(nbs), dim3(64), 0, s->stream, a, (const double *)col, -0.5 * a.dt,
-                           0.5, i0, i1, 1.0, 1);
+        hipLaunchKernelGGL(k_adj_init_cols, dim3(i1 - i0), dim3(256), 0, s->stream, a, (const double *)a.lby,
+                           -0.5 * a.dt, 0.5, i0, col);
+        hipLaunchKernelGGL(k_adj_slices, dim3(1), dim3(256), 0, s->stream, a, (const double *)col, i0, i1, 1.0);
     }
     HIPCHK(s, hipGetLastError());
     return LBW_OK;
