@@ -46,9 +46,9 @@ def bytes_per_lu(dims, closure, storage):
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake2d_lec_fp32", "fp32"): 301.6e6,
     ("wake2d_lec_fp32", "fp64"): 605.6e6,
-    ("wake2d_warmc", "fp64"): 7254.5e6,
-    ("wake2d_warmc", "fp32"): 3914.4e6,
-    ("wake2d_warmc", "fp16dev"): 2108.9e6,
+    ("wake2d_warmc", "fp64"): 6867.3e6,
+    ("wake2d_warmc", "fp32"): 3954.7e6,
+    ("wake2d_warmc", "fp16dev"): 2119.3e6,
 }
 
 

@@ -23,6 +23,15 @@ pytestmark = pytest.mark.gpu
 FIELDS = ("n", "mz", "mx", "ez")
 
 
+def _report(name, report):
+    """Write the error report as JSON into $LBW_REPORT_DIR when it is set."""
+    d = os.environ.get("LBW_REPORT_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, name), "w") as f:
+            json.dump(report, f)
+
+
 def _run(w, storage, steps, extra=()):
     from paper_2309_04872_amd.sim import Sim
 
@@ -54,9 +63,7 @@ def test_warm_wake_precision_variants():
         report[storage] = errs
         print(storage, errs, flush=True)
         assert all(e <= bound for e in errs.values()), (storage, errs)
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/precision_wake2d_warmc.json", "w") as f:
-        json.dump(report, f)
+    _report("precision_wake2d_warmc.json", report)
 
 
 def test_lec_wake_precision_variants_full_length():
@@ -72,6 +79,4 @@ def test_lec_wake_precision_variants_full_length():
         report[storage] = errs
         print(storage, errs, flush=True)
         assert all(e <= bound for e in errs.values()), (storage, errs)
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/precision_wake2d_lec.json", "w") as f:
-        json.dump(report, f)
+    _report("precision_wake2d_lec.json", report)
