@@ -371,19 +371,17 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 // 1D fused step: TZ nodes per workgroup plus a ring of one node on each side;
 // E_z sits on the nodes and its update is local: E^n = E^{n-1} + dt (n u + n_b).
 template <int CL, class ST, int TZ>
-__global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
+__device__ __forceinline__ void step1d_tile(const StepArgs &a, int tile, double (*s_g)[TZ + 2])
 {
     using L = Lattice<1>;
     using CT = typename Store<ST>::ct;
     constexpr int Q = L::Q;
     constexpr int K = NScal<1, CL>::K;
-    constexpr int NG = CL == LEC ? 1 : 3;  // phi | theta^0z, theta^zz, lambda u_z
-    __shared__ double s_g[NG][TZ + 2];
 
     const int tid = threadIdx.x;
     const int nz = a.nz, bcz = a.bcz;
     const size_t nc = (size_t)a.ncell;
-    const int z0 = blockIdx.x * TZ;
+    const int z0 = tile * TZ;
     const ST *src = (const ST *)a.src;
     ST *dst = (ST *)a.dst;
     const double two_over_d = a.two_over_d, a_lec = a.a_lec;
@@ -442,43 +440,83 @@ __global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
     R1 r;
     recover(A, tid + 1, r);
     __syncthreads();
-    if (!active) return;
-
-    const double dt = a.dt;
-    const double n = A[0], uz = r.uz;
-    const size_t c = (size_t)gz;
-    double Ez = a.ez_in[c];
-    if (a.do_maxwell) {
-        const double jb = driver_density<1>(a.drv, gz * a.delta, 0.0, (a.step - 0.5) * dt);
-        Ez = Ez + dt * (n * uz + jb);
-    }
-    a.ez_out[c] = Ez;
-    const int rp = map_node(gz + 1, nz, bcz) - (z0 - 1), rm = map_node(gz - 1, nz, bcz) - (z0 - 1);
-    auto Dz = [&](int g) { return (s_g[g][rp] - s_g[g][rm]) * a.inv2d; };
-    double F[K];
-    if constexpr (CL == LEC) {
-        F[0] = 0.0;
-        F[1] = -a.mu * Dz(0) - n * Ez;
-    } else {
-        const double th0z = r.w.th0z, thzz = r.w.thzz, luz = r.w.luz, th00 = r.w.th00;
-        double l00, l0z, lluz;
-        if (a.lag_init) {
-            l00 = th00; l0z = th0z; lluz = luz;
-        } else {
-            l00 = a.lag[0 * nc + c]; l0z = a.lag[1 * nc + c]; lluz = a.lag[2 * nc + c];
+    if (active) {
+        const double dt = a.dt;
+        const double n = A[0], uz = r.uz;
+        const size_t c = (size_t)gz;
+        double Ez = a.ez_in[c];
+        if (a.do_maxwell) {
+            const double jb = driver_density<1>(a.drv, gz * a.delta, 0.0, (a.step - 0.5) * dt);
+            Ez = Ez + dt * (n * uz + jb);
         }
-        a.lag[0 * nc + c] = th00; a.lag[1 * nc + c] = th0z; a.lag[2 * nc + c] = luz;
-        const double idt = 1.0 / dt;
-        F[0] = 0.0;
-        F[1] = -(th00 - l00) * idt - Dz(0) - n * (Ez * uz);
-        F[2] = -(th0z - l0z) * idt - Dz(1) - n * Ez;
-        F[3] = -2.0 * th0z * ((luz - lluz) * idt) - 2.0 * thzz * Dz(2) - 2.0 * (Ez * th0z);
+        a.ez_out[c] = Ez;
+        const int rp = map_node(gz + 1, nz, bcz) - (z0 - 1), rm = map_node(gz - 1, nz, bcz) - (z0 - 1);
+        auto Dz = [&](int g) { return (s_g[g][rp] - s_g[g][rm]) * a.inv2d; };
+        double F[K];
+        if constexpr (CL == LEC) {
+            F[0] = 0.0;
+            F[1] = -a.mu * Dz(0) - n * Ez;
+        } else {
+            const double th0z = r.w.th0z, thzz = r.w.thzz, luz = r.w.luz, th00 = r.w.th00;
+            double l00, l0z, lluz;
+            if (a.lag_init) {
+                l00 = th00; l0z = th0z; lluz = luz;
+            } else {
+                l00 = a.lag[0 * nc + c]; l0z = a.lag[1 * nc + c]; lluz = a.lag[2 * nc + c];
+            }
+            a.lag[0 * nc + c] = th00; a.lag[1 * nc + c] = th0z; a.lag[2 * nc + c] = luz;
+            const double idt = 1.0 / dt;
+            F[0] = 0.0;
+            F[1] = -(th00 - l00) * idt - Dz(0) - n * (Ez * uz);
+            F[2] = -(th0z - l0z) * idt - Dz(1) - n * Ez;
+            F[3] = -2.0 * th0z * ((luz - lluz) * idt) - 2.0 * thzz * Dz(2) - 2.0 * (Ez * th0z);
+        }
+        collide_all<1, K, CT>(s, A, aref, F, uz, 0.0, a.lam, a.omega, dt);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) Store<ST>::st(dst + (size_t)(k * Q + q) * nc, (int)c, s[k][q]);
     }
-    collide_all<1, K, CT>(s, A, aref, F, uz, 0.0, a.lam, a.omega, dt);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) Store<ST>::st(dst + (size_t)(k * Q + q) * nc, (int)c, s[k][q]);
+    __syncthreads();  // the LDS slots are reused by the next tile or step
+}
+
+// One launch per step: one tile per workgroup.
+template <int CL, class ST, int TZ>
+__global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
+{
+    constexpr int NG = CL == LEC ? 1 : 3;  // phi | theta^0z, theta^zz, lambda u_z
+    __shared__ double s_g[NG][TZ + 2];
+    step1d_tile<CL, ST, TZ>(a, blockIdx.x, s_g);
+}
+
+// All steps of one lbw_step call in one cooperative launch (1D grids small
+// enough for every workgroup to be resident): the workgroups sweep their
+// tiles, then wait for the whole grid before the next step reads its
+// neighbours. Buffers alternate as between separate launches; a.src / a.dst
+// and the E_z arrays are those of the first step.
+template <int CL, class ST, int TZ>
+__global__ __launch_bounds__(TZ) void k_step1d_persist(StepArgs a, int nsteps)
+{
+    constexpr int NG = CL == LEC ? 1 : 3;
+    __shared__ double s_g[NG][TZ + 2];
+    const int ntiles = (a.nz + TZ - 1) / TZ;
+    for (int t = 0; t < nsteps; ++t) {
+        StepArgs b = a;
+        if (t & 1) {
+            b.src = a.dst;
+            b.dst = (void *)a.src;
+            b.ez_in = a.ez_out;
+            b.ez_out = (double *)a.ez_in;
+        }
+        if (t > 0) {
+            b.do_pull = 1;
+            b.do_maxwell = 1;
+            b.lag_init = 0;
+        }
+        b.step = a.step + t;
+        for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) step1d_tile<CL, ST, TZ>(b, tile, s_g);
+        __ockl_grid_sync();
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -141,6 +141,7 @@ struct lbw_sim {
     int ev_used;
     double kernel_ms;
     long launches, pending_launches;
+    int persist;  // 1D: workgroups of the persistent kernel (-1: not queried yet, 0: unavailable)
 };
 
 static lbw_status fail(lbw_sim *s, lbw_status code, const std::string &m)
@@ -212,6 +213,38 @@ template <int DIM, int CL, class ST> struct Impl {
             hipLaunchKernelGGL((k_step1d<CL, ST, TZ1>), grid, dim3(TZ1), 0, st, a);
         }
     }
+    // Workgroups of the persistent 1D kernel that can all be resident at once
+    // (0: no cooperative launch on this device).
+    static int persist_grid(int nz)
+    {
+        if constexpr (DIM == 1) {
+            int dev = 0, coop = 0, cus = 0, per = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return 0;
+            if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+                return 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step1d_persist<CL, ST, TZ1>, TZ1, 0) !=
+                hipSuccess)
+                return 0;
+            const int ntiles = (nz + TZ1 - 1) / TZ1;
+            const int maxg = per * cus;
+            return ntiles < maxg ? ntiles : maxg;
+        } else {
+            return 0;
+        }
+    }
+    static hipError_t step_persist(const StepArgs &a, int nsteps, int grid, hipStream_t st)
+    {
+        if constexpr (DIM == 1) {
+            StepArgs aa = a;
+            int ns = nsteps;
+            void *args[] = {&aa, &ns};
+            return hipLaunchCooperativeKernel((const void *)k_step1d_persist<CL, ST, TZ1>, dim3(grid), dim3(TZ1), args,
+                                              0, st);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     static void finish(const StepArgs &a, double *jz, double *jx, hipStream_t st)
     {
         const int nb = (a.ncell + 255) / 256;
@@ -243,6 +276,8 @@ template <int DIM, int CL, class ST> struct Impl {
 
 struct Ops {
     void (*step)(const StepArgs &, hipStream_t);
+    int (*persist_grid)(int);
+    hipError_t (*step_persist)(const StepArgs &, int, int, hipStream_t);
     void (*finish)(const StepArgs &, double *, double *, hipStream_t);
     void (*init_pops)(void *, const double *, const double *, const double *, const double *, int,
                       double, hipStream_t);
@@ -253,7 +288,7 @@ struct Ops {
 template <int DIM, int CL, class ST> Ops ops_of()
 {
     using I = Impl<DIM, CL, ST>;
-    return Ops{&I::step, &I::finish, &I::init_pops, &I::read_moment, &I::diag};
+    return Ops{&I::step, &I::persist_grid, &I::step_persist, &I::finish, &I::init_pops, &I::read_moment, &I::diag};
 }
 
 template <int DIM, int CL> Ops ops_st(int storage)
@@ -332,6 +367,7 @@ lbw_status lbw_create(const lbw_grid_desc *grid, void *ws, size_t ws_bytes, void
     s->kernel_ms = 0.0;
     s->launches = 0;
     s->pending_launches = 0;
+    s->persist = -1;
     *out = s;
     return LBW_OK;
 }
@@ -577,18 +613,34 @@ lbw_status lbw_step(lbw_sim *s, int nsteps)
         }
         HIPCHK(s, hipEventRecord(s->ev[s->ev_used++], s->stream));
     }
-    for (int t = 0; t < nsteps; ++t) {
+    if (s->g.dims == 1 && s->persist < 0) s->persist = ops.persist_grid(s->g.nz);
+    if (s->g.dims == 1 && s->persist > 0 && nsteps >= 2) {
+        // 1D: every step of the call in one cooperative launch
         StepArgs a = base_args(s);
         set_io(s, a);
         a.do_pull = s->canonical ? 0 : 1;
         a.do_maxwell = s->canonical ? 0 : 1;
         a.lag_init = s->lag_valid ? 0 : 1;
-        ops.step(a, s->stream);
-        s->pcur ^= 1;
-        s->fcur ^= 1;
+        HIPCHK(s, ops.step_persist(a, nsteps, s->persist, s->stream));
+        s->pcur ^= nsteps & 1;
+        s->fcur ^= nsteps & 1;
         s->canonical = false;
         s->lag_valid = true;
-        s->step++;
+        s->step += nsteps;
+    } else {
+        for (int t = 0; t < nsteps; ++t) {
+            StepArgs a = base_args(s);
+            set_io(s, a);
+            a.do_pull = s->canonical ? 0 : 1;
+            a.do_maxwell = s->canonical ? 0 : 1;
+            a.lag_init = s->lag_valid ? 0 : 1;
+            ops.step(a, s->stream);
+            s->pcur ^= 1;
+            s->fcur ^= 1;
+            s->canonical = false;
+            s->lag_valid = true;
+            s->step++;
+        }
     }
     HIPCHK(s, hipGetLastError());
     if (s->timing) {
