@@ -52,6 +52,49 @@ TRAFFIC_BYTES_PER_LAUNCH = {
 }
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_bandwidth_gbs(stream, nbytes=1 << 30, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time) of a plain
+    torch copy on the same GPU, HIP events on ``stream``."""
+    import torch
+
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    with torch.cuda.stream(stream):
+        y.copy_(x)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            y.copy_(x)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+def one_thread(fn, seconds):
+    """MLUPS of fn(cells_steps_counter) on one oracle thread."""
+    import oracle
+
+    n0 = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        return fn(seconds)
+    finally:
+        oracle.set_threads(n0)
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The CPU oracle (test infrastructure, FP64) on a bounded sample of the
     same workload: the full grid for as many steps as fit the budget."""
@@ -63,18 +106,24 @@ def cpu_baseline(w, budget_s=12.0):
                       sigma_x=w["sigma_x"], z0=w["z0"])
     o.init()
     o.step(1)  # first touch of the arrays
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        o.step(1)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
     cells = w["nz"] * w["nx"]
+
+    def run(seconds):
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            o.step(1)
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        return n, time.perf_counter() - t0
+
+    n, dt = run(budget_s)
+    n1, dt1 = one_thread(run, budget_s / 4)
     return {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"full {w['nx']}x{w['nz']} grid, {n} FP64 steps ({dt:.1f} s) of the same workload"}
+            "kind": "oracle", "value_1core": cells * n1 / dt1 / 1e6, "cpu_model": cpu_model(),
+            "sample": f"full {w['nx']}x{w['nz']} grid, {n} FP64 steps ({dt:.1f} s) of the same workload; "
+                      f"{n1} steps on one thread ({dt1:.1f} s)"}
 
 
 def batch_bytes_per_step(insts):
@@ -105,10 +154,24 @@ def cpu_baseline_batch(insts, budget_s=12.0):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+
+    def first(seconds):
+        d = insts[0]
+        o = oracle.Oracle(1, d["nz"], 1, delta=d["delta"], dt=d["dt"], tau_tilde=d["tau_tilde"],
+                          closure=0 if d["closure"] == "lec" else 1, dvel=d["dvel"], mu=d["mu"],
+                          alpha=d["alpha"], sigma_z=d["sigma_z"], z0=d["z0"])
+        o.init()
+        t1 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t1 < seconds:
+            o.step(64)
+            k += 64
+        return d["nz"] * k / (time.perf_counter() - t1) / 1e6
+
     return {"value": cells_steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "value_1core": one_thread(first, budget_s / 4), "cpu_model": cpu_model(),
             "sample": f"first {len(used)} instances of the scan ({sum(used)} nodes), 256 FP64 steps each, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s; one thread: the first instance"}
 
 
 def bench_batch(args):
@@ -137,6 +200,7 @@ def bench_batch(args):
     wall = time.perf_counter() - t0
     ms_total = ev0.elapsed_time(ev1)
     k_ms = b.last_ms()  # HIP events on the batch's stream around the one launch
+    copy_gbs = copy_bandwidth_gbs(b.stream)
     bad = b.nonfinite()
     bps = batch_bytes_per_step(insts)
     # HBM-side bytes per step measured with rocprofv3 (FETCH_SIZE, WRITE_SIZE,
@@ -167,6 +231,7 @@ def bench_batch(args):
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_per_step * steps, "kernel": "k_batch1d",
+            "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
             "kernel_avg_us": k_ms * 1e3, "bytes_per_step": bps, "launches": 1,
         },
         "wall_s": wall,
@@ -309,6 +374,7 @@ def main():
     k_ms, k_n = s.get_timing()
     s.set_timing(False)
     k_avg_s = k_ms / max(k_n, 1) / 1e3
+    copy_gbs = copy_bandwidth_gbs(s.stream)
     blu = bytes_per_lu(w["dims"], w["closure"], w["storage"])
     achieved = blu * cells / k_avg_s / 1e9
     traffic = TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, w["storage"]))
@@ -335,7 +401,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_step2d" if w["dims"] == 2 else "k_step1d",
+            "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+            "kernel": "k_step2d" if w["dims"] == 2 else "k_step1d_persist",
             "kernel_avg_us": k_avg_s * 1e6, "bytes_per_lu": blu, "launches": k_n,
         },
         "wall_s": wall,
