@@ -58,6 +58,9 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+SLAB, AXI = 0, 1  # geometries: Cartesian (z, x) | axisymmetric (z, r)
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("dims", ctypes.c_int), ("nz", ctypes.c_int), ("nx", ctypes.c_int),
@@ -69,6 +72,7 @@ class _Params(ctypes.Structure):
         ("z0", ctypes.c_double), ("x0", ctypes.c_double),
         ("nslices", ctypes.c_int), ("slice_zmin", ctypes.c_double),
         ("slice_zmax", ctypes.c_double), ("slice_w", ctypes.POINTER(ctypes.c_double)),
+        ("geom", ctypes.c_int),
     ]
 
 
@@ -135,7 +139,7 @@ class Oracle:
     def __init__(self, dims, nz, nx=1, delta=2 * np.pi / 128, dt=None, tau_tilde=None,
                  closure=LEC, dvel=None, bc_z=OPEN, bc_x=OPEN, mu=1e-3, alpha=0.0,
                  sigma_z=1.0, sigma_x=1.0, z0=None, x0=0.0, slice_w=None,
-                 slice_zmin=0.0, slice_zmax=0.0):
+                 slice_zmin=0.0, slice_zmax=0.0, geom=0):
         if dt is None:
             dt = 0.1 * delta
         if tau_tilde is None:
@@ -146,7 +150,7 @@ class Oracle:
             z0 = 6.0 * sigma_z
         self._keep = None
         p = _Params(dims, nz, nx, delta, dt, tau_tilde, closure, float(dvel), bc_z, bc_x,
-                    mu, alpha, sigma_z, sigma_x, z0, x0, 0, slice_zmin, slice_zmax, None)
+                    mu, alpha, sigma_z, sigma_x, z0, x0, 0, slice_zmin, slice_zmax, None, int(geom))
         if slice_w is not None:
             w = np.ascontiguousarray(slice_w, dtype=np.float64)
             self._keep = w

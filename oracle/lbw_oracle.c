@@ -67,6 +67,7 @@ enum { G_TH00 = 0, G_TH0Z, G_TH0X, G_LUZ, G_LUX, NG };
 struct orc_state {
     orc_params p;
     double *slice_w;
+    int mirror_x[9];  /* direction with e_x reversed (2D) */
     int Q, K, nz, nx, ncell;
     const int *ez, *ex;
     const double *w;
@@ -128,6 +129,7 @@ static int ycell(const orc_state *s, int j, int i, int sz, int sx)
 static double node_z(const orc_state *s, double i) { return i * s->p.delta; }
 static double node_x(const orc_state *s, double j)
 {
+    if (s->p.geom == ORC_GEOM_AXI) return (j + 0.5) * s->p.delta; /* r_j */
     return (j - 0.5 * (s->nx - 1)) * s->p.delta;
 }
 
@@ -390,9 +392,15 @@ static void node_fields(orc_state *s)
         for (int i = 0; i < nz; ++i) {
             int c = j * nz + i;
             s->En_z[c] = 0.5 * (EZ_AT(j, i - 1) + EZ_AT(j, i));
-            s->En_x[c] = 0.5 * (EX_AT(j - 1, i) + EX_AT(j, i));
-            s->Bn_y[c] = 0.25 * (BY_AT(s->Bh, j, i) + BY_AT(s->Bh, j, i - 1) +
-                                 BY_AT(s->Bh, j - 1, i) + BY_AT(s->Bh, j - 1, i - 1));
+            if (s->p.geom == ORC_GEOM_AXI && j == 0) {
+                /* E_r and B_phi are odd in r: zero on the axis (r_{-1/2} = 0) */
+                s->En_x[c] = 0.5 * EX_AT(j, i);
+                s->Bn_y[c] = 0.25 * (BY_AT(s->Bh, j, i) + BY_AT(s->Bh, j, i - 1));
+            } else {
+                s->En_x[c] = 0.5 * (EX_AT(j - 1, i) + EX_AT(j, i));
+                s->Bn_y[c] = 0.25 * (BY_AT(s->Bh, j, i) + BY_AT(s->Bh, j, i - 1) +
+                                     BY_AT(s->Bh, j - 1, i) + BY_AT(s->Bh, j - 1, i - 1));
+            }
         }
 }
 
@@ -428,6 +436,19 @@ static void forces(orc_state *s)
                 F[L_AZ * nc + c] = -mu * ddz(s, RR(R_PHI), j, i) - n * (Ez + ux * By);
                 if (s->p.dims == 2)
                     F[L_AX * nc + c] = -mu * ddx(s, RR(R_PHI), j, i) - n * (Ex - uz * By);
+                if (s->p.geom == ORC_GEOM_AXI) {
+                    /* App. A: the cylindrical part of the divergence, -u_r A / r,
+                     * as a source of every advected scalar (x is r here) */
+                    double ir = 1.0 / node_x(s, j);
+                    double An = n, Az = 0.0, Ar = 0.0;
+                    for (int q = 0; q < s->Q; ++q) {
+                        Az += s->f[(L_AZ * s->Q + q) * nc + c];
+                        Ar += s->f[(L_AX * s->Q + q) * nc + c];
+                    }
+                    F[0 * nc + c] -= ux * An * ir;
+                    F[L_AZ * nc + c] -= ux * Az * ir;
+                    F[L_AX * nc + c] -= ux * Ar * ir;
+                }
             } else {
                 /* eq. lb-ade-warmc-comps-F written out in App. A; Cartesian
                  * slab: the 1/r terms vanish, r -> x, phi -> y, c = e = 1.
@@ -494,15 +515,29 @@ static void collide_stream(orc_state *s)
             }
         }
     }
-    /* Streaming: f_i(x + xi_i dt) = f*_i(x), read as a pull from x - e_i. */
+    /* Streaming: f_i(x + xi_i dt) = f*_i(x), read as a pull from x - e_i.
+     * Axisymmetric geometry: the axis lies midway between row 0 and the
+     * ghost row -1, and the ghost holds the mirror image of row 0: the
+     * populations of the mirrored direction (eq. reflective-bc), with the
+     * sign reversed for the one scalar that is odd under r -> -r (the radial
+     * momentum A_r). This is our reading of the axis rule of Sec. 2.2 for
+     * this node layout: a plain copy (eq. open-bc) for the even scalars
+     * would let mass cross the axis, which the cylindrical divergence of
+     * App. A does not allow. */
+    const int axi = s->p.geom == ORC_GEOM_AXI;
 #pragma omp parallel for
     for (int j = 0; j < nx; ++j)
         for (int i = 0; i < nz; ++i) {
             int c = j * nz + i;
             for (int q = 0; q < Q; ++q) {
-                int src = cell(s, j - (s->ex ? s->ex[q] : 0), i - s->ez[q]);
-                for (int k = 0; k < K; ++k)
-                    f[(k * Q + q) * nc + c] = fs[(k * Q + q) * nc + src];
+                int sj = j - (s->ex ? s->ex[q] : 0);
+                int src = cell(s, sj, i - s->ez[q]);
+                for (int k = 0; k < K; ++k) {
+                    int qs = q;
+                    double sg = 1.0;
+                    if (axi && sj < 0) { qs = s->mirror_x[q]; if (k == L_AX) sg = -1.0; }
+                    f[(k * Q + q) * nc + c] = sg * fs[(k * Q + qs) * nc + src];
+                }
             }
         }
 }
@@ -541,6 +576,12 @@ static void maxwell(orc_state *s)
             double jb = -orc_bunch(s, node_z(s, i + 0.5), node_x(s, j), th);
             double curl_x = -(BY_AT(s->By, j, i) - BY_AT(s->By, j, i - 1)) / d;
             double curl_z = (BY_AT(s->By, j, i) - BY_AT(s->By, j - 1, i)) / d;
+            if (s->p.geom == ORC_GEOM_AXI) {
+                /* (1/r) d_r (r B_phi) at r_j = (j + 1/2) d from B_phi at
+                 * r = (j + 1) d and j d (the latter on the axis for j = 0) */
+                double bm = j > 0 ? BY_AT(s->By, j - 1, i) : 0.0;
+                curl_z = ((j + 1.0) * BY_AT(s->By, j, i) - j * bm) / ((j + 0.5) * d);
+            }
             s->Ex[c] = s->Ex[c] + dt * (curl_x - jx);
             s->Ez[c] = s->Ez[c] + dt * (curl_z - jz - jb);
         }
@@ -581,6 +622,10 @@ orc_state *orc_create(const orc_params *p)
     if (p->dims == 2 && p->nx < 2) return NULL;
     if (p->dims == 1 && p->nx != 1) return NULL;
     if (!(p->tau_tilde > 0.5) || !(p->dt > 0) || !(p->delta > 0)) return NULL;
+    if (p->geom != ORC_GEOM_SLAB && p->geom != ORC_GEOM_AXI) return NULL;
+    if (p->geom == ORC_GEOM_AXI &&
+        (p->dims != 2 || p->closure != ORC_LEC || p->bc_x != ORC_BC_OPEN || p->x0 != 0.0))
+        return NULL;
     orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
     s->p = *p;
     if (p->nslices > 0) {
@@ -596,6 +641,9 @@ orc_state *orc_create(const orc_params *p)
         s->K = p->closure == ORC_LEC ? 2 : 4;
     } else {
         s->Q = 9; s->ez = D2_ez; s->ex = D2_ex; s->w = D2_w;
+        for (int q = 0; q < 9; ++q)
+            for (int m = 0; m < 9; ++m)
+                if (D2_ez[m] == D2_ez[q] && D2_ex[m] == -D2_ex[q]) s->mirror_x[q] = m;
         s->K = p->closure == ORC_LEC ? 3 : 8;
     }
     size_t nc = (size_t)s->ncell;
@@ -705,6 +753,8 @@ int orc_init(orc_state *s, const double *n_init, const double *uz_init,
                 for (int i = 0; i < nz; ++i) {
                     double xh = node_x(s, j + 0.5) - s->p.x0;
                     double tr = -sx * sqrt(M_PI / 2.0) * erf(xh / (sqrt(2.0) * sx));
+                    if (s->p.geom == ORC_GEOM_AXI) /* Gauss in r: (1/r) d_r (r E_r) = -n_b */
+                        tr = -sx * sx * (1.0 - exp(-xh * xh / (2.0 * sx * sx))) / xh;
                     double ze = node_z(s, i) - s->p.z0;
                     double zb = node_z(s, i + 0.5) - s->p.z0 + 0.5 * s->p.dt;
                     s->Ex[j * nz + i] = s->p.alpha * slice_weight(s, ze) *
@@ -860,7 +910,8 @@ int orc_get(orc_state *s, int which, double *out)
 int orc_diagnostics(orc_state *s, double *out)
 {
     const int nc = s->ncell, nz = s->nz, nx = s->nx;
-    const double dV = s->p.dims == 1 ? s->p.delta : s->p.delta * s->p.delta;
+    const double dV0 = s->p.dims == 1 ? s->p.delta : s->p.delta * s->p.delta;
+    const int axi = s->p.geom == ORC_GEOM_AXI;
     const double Lam = s->p.delta / s->p.dt, t = s->step * s->p.dt, d = s->p.delta;
     long fb = s->fallbacks;
     recover_all(s, s->f, s->R1);
@@ -872,6 +923,10 @@ int orc_diagnostics(orc_state *s, double *out)
             int c = j * nz + i;
             double n = R[R_N * nc + c], uz = R[R_UZ * nc + c], ux = R[R_UX * nc + c];
             double g = R[R_GAM * nc + c];
+            /* axisymmetric: volume 2 pi r per unit cell area, nodes at r_j,
+             * E_r and B_phi at r_{j+1/2} */
+            const double dV = axi ? 2.0 * M_PI * node_x(s, j) * dV0 : dV0;
+            const double dVh = axi ? 2.0 * M_PI * node_x(s, j + 0.5) * dV0 : dV0;
             sn += n * dV;
             if (s->p.dims == 1) {
                 fe += 0.5 * s->Ez[c] * s->Ez[c] * dV;
@@ -880,8 +935,8 @@ int orc_diagnostics(orc_state *s, double *out)
                 int rz = s->p.bc_z == ORC_BC_PERIODIC || i < nz - 1;
                 int rx = s->p.bc_x == ORC_BC_PERIODIC || j < nx - 1;
                 if (rz) fe += 0.5 * s->Ez[c] * s->Ez[c] * dV;
-                if (rx) fe += 0.5 * s->Ex[c] * s->Ex[c] * dV;
-                if (rz && rx) fe += 0.5 * s->By[c] * s->By[c] * dV;
+                if (rx) fe += 0.5 * s->Ex[c] * s->Ex[c] * dVh;
+                if (rz && rx) fe += 0.5 * s->By[c] * s->By[c] * dVh;
             }
             ke += n * (g - 1.0) * dV;
             double um = sqrt(uz * uz + ux * ux) / Lam;
@@ -891,6 +946,11 @@ int orc_diagnostics(orc_state *s, double *out)
                 div = (s->Ez[cell(s, j, i + 1)] - s->Ez[cell(s, j, i - 1)]) / (2.0 * d);
             } else {
                 div = (EZ_AT(j, i) - EZ_AT(j, i - 1)) / d + (EX_AT(j, i) - EX_AT(j - 1, i)) / d;
+                if (axi) {
+                    double em = j > 0 ? EX_AT(j - 1, i) : 0.0;
+                    div = (EZ_AT(j, i) - EZ_AT(j, i - 1)) / d +
+                          ((j + 1.0) * EX_AT(j, i) - j * em) / ((j + 0.5) * d);
+                }
             }
             double rho = 1.0 - n - orc_bunch(s, node_z(s, i), node_x(s, j), t);
             g2 += (div - rho) * (div - rho);

@@ -10,7 +10,8 @@
  * Units: plasma units, c = m_e = e = 1, ion density n_i = 1, electrons carry
  * charge -1; time in 1/omega_p, length in 1/k_p, fields in m_e c omega_p / e.
  *
- * Grid: node (j, i) sits at z_i = i*delta, x_j = (j - (nx-1)/2)*delta;
+ * Grid: node (j, i) sits at z_i = i*delta, x_j = (j - (nx-1)/2)*delta
+ * (axisymmetric geometry: r_j = (j + 1/2)*delta);
  * arrays are [nx][nz] with z fastest. In 2D the Yee arrays hold
  *   Ez[j][i] at (z_{i+1/2}, x_j), Ex[j][i] at (z_i, x_{j+1/2}),
  *   By[j][i] at (z_{i+1/2}, x_{j+1/2}).
@@ -62,7 +63,14 @@ typedef struct {
     int nslices;           /* 0: plain Gaussian; else piecewise-constant slices */
     double slice_zmin, slice_zmax; /* slice span in zeta = z - z0 - t */
     const double *slice_w; /* nslices weights (copied) */
+    /* ORC_GEOM_SLAB: Cartesian (z, x). ORC_GEOM_AXI: axisymmetric (z, r), the
+     * 3D3V geometry of Sec. 2.2 and App. A (2D, local-equilibrium closure,
+     * bc_x open at the outer radius; x0 must be 0). Node j sits at
+     * r_j = (j + 1/2) delta; the ghost row j = -1 mirrors the axis. */
+    int geom;
 } orc_params;
+
+enum { ORC_GEOM_SLAB = 0, ORC_GEOM_AXI = 1 };
 
 typedef struct orc_state orc_state;
 
