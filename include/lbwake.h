@@ -62,6 +62,16 @@ typedef enum { LBW_LEC = 0, LBW_WARMC = 1 } lbw_closure;
 typedef enum { LBW_FP64 = 0, LBW_FP32 = 1, LBW_FP16DEV = 2 } lbw_storage;
 typedef enum { LBW_BC_OPEN = 0, LBW_BC_PERIODIC = 1 } lbw_bc;
 
+/* Transverse geometry of a 2D grid. SLAB: Cartesian (z, x), node row j at
+ * x_j = (j - (nx-1)/2) delta. AXI: the axisymmetric (z, r) geometry of
+ * Sec. 2.2 and App. A (local-equilibrium closure, open outer radius): node
+ * row j at r_j = (j + 1/2) delta, the cylindrical part of every divergence
+ * as a source -u_r A / r, the E_z update with (1/r) d_r (r B_phi), E_r and
+ * B_phi zero on the axis; below the axis the populations are the mirror
+ * image of row 0 (mirrored directions, eq. reflective-bc, with the radial
+ * momentum A_r negated). The x arrays then run over r. */
+typedef enum { LBW_GEOM_SLAB = 0, LBW_GEOM_AXI = 1 } lbw_geom;
+
 /* Fluid observables for lbw_read_moment (one value per node). */
 typedef enum {
     LBW_N = 0,      /* lab-frame electron density n */
@@ -95,6 +105,8 @@ typedef struct {
     double dvel;       /* D, dimension of the kinetic momentum space: 1 or 3 */
     int storage;       /* lbw_storage */
     int bc_z, bc_x;    /* lbw_bc */
+    int geom;          /* lbw_geom (2D; SLAB in 1D). Zero-initialise the
+                          descriptor: 0 is the Cartesian slab */
 } lbw_grid_desc;
 
 typedef struct {
@@ -117,11 +129,13 @@ typedef struct {
 typedef struct lbw_sim lbw_sim;
 
 /* Bytes of device workspace a simulation of this grid needs (0 if the
- * descriptor is invalid). The workspace must be 256-byte aligned. */
+ * descriptor is invalid or unsupported). The workspace must be 256-byte
+ * aligned. */
 size_t lbw_workspace_bytes(const lbw_grid_desc *grid);
 
 /* Validate the grid (tau~ > 1/2, Courant dt <= delta / sqrt(dims)) and bind
- * the caller's workspace and stream (hipStream_t, NULL = default stream). */
+ * the caller's workspace and stream (hipStream_t, NULL = default stream).
+ * LBW_ERR_UNSUPPORTED for the warm closure in the axisymmetric geometry. */
 lbw_status lbw_create(const lbw_grid_desc *grid, void *device_workspace,
                       size_t workspace_bytes, void *hip_stream, lbw_sim **out);
 
@@ -139,7 +153,9 @@ lbw_status lbw_init_moments(lbw_sim *sim, double mu, const double *A,
 
 /* Rigid driver (eq. bunch-density with rms widths). init_fields = 1 also sets
  * E, B to the field of the bunch alone at t = 0 (Sec. 5): 1D the causal
- * Gauss-consistent E_z, 2D the vacuum solution travelling at c. */
+ * Gauss-consistent E_z, 2D the vacuum solution travelling at c (in the
+ * axisymmetric geometry from the cylindrical Gauss law; there the bunch sits
+ * on the axis, x0 = 0, else LBW_ERR_ARG). */
 lbw_status lbw_init_driver(lbw_sim *sim, const lbw_driver_desc *driver,
                            int init_fields);
 
@@ -200,7 +216,7 @@ lbw_status lbw_load_state_device(lbw_sim *sim, const void *device_src, long step
  * Discrete adjoint of the 2D local-equilibrium step (Sec. 2.2, Sec. 3.1,
  * Sec. 5): the transposed Jacobian of one step of lbw_step, and the
  * derivatives of the driver's slice weights (per-slice current profile) in
- * the bunch current and in the initial fields. 2D, LBW_LEC, any storage
+ * the bunch current and in the initial fields. 2D slab, LBW_LEC, any storage
  * (the adjoint itself is FP64), at most 1024 slices; LBW_ERR_UNSUPPORTED
  * otherwise, LBW_ERR_STATE when the driver has no slices.
  *

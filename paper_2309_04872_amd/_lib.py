@@ -16,6 +16,7 @@ STATUS = {
 CLOSURES = {"lec": 0, "warmc": 1}
 STORAGE = {"fp64": 0, "fp32": 1, "fp16dev": 2}
 BCS = {"open": 0, "periodic": 1}
+GEOMS = {"slab": 0, "axi": 1}
 MOMENTS = {
     "n": 0, "uz": 1, "ux": 2, "gamma": 3, "n0": 4, "p0": 5, "lambda": 6, "thzz": 7, "thxx": 8,
     "thyy": 9, "thxz": 10, "ppar": 11, "mz": 12, "mx": 13,
@@ -43,7 +44,7 @@ class GridDesc(ctypes.Structure):
         ("dims", ctypes.c_int), ("nz", ctypes.c_int), ("nx", ctypes.c_int),
         ("delta", ctypes.c_double), ("dt", ctypes.c_double), ("tau_tilde", ctypes.c_double),
         ("closure", ctypes.c_int), ("dvel", ctypes.c_double), ("storage", ctypes.c_int),
-        ("bc_z", ctypes.c_int), ("bc_x", ctypes.c_int),
+        ("bc_z", ctypes.c_int), ("bc_x", ctypes.c_int), ("geom", ctypes.c_int),
     ]
 
 

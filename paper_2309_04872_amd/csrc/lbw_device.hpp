@@ -41,6 +41,11 @@ template <> struct Lattice<2> {
     {
         return q == 0 ? 4.0 / 9.0 : (q < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
     }
+    // direction with e_x reversed (reflection through the axis x = 0)
+    __device__ static constexpr int mx(int q)
+    {
+        return q == 3 ? 4 : q == 4 ? 3 : q == 5 ? 7 : q == 7 ? 5 : q == 6 ? 8 : q == 8 ? 6 : q;
+    }
 };
 
 // Number of advected scalars (eq. lb-ade-lec-comps-A, eq. lb-ade-warmc-comps-A):
@@ -107,6 +112,14 @@ __device__ __forceinline__ int map_node(int i, int n, int bc)
 __device__ __forceinline__ int map_stag(int i, int n, int bc)
 {
     return bc == BC_PERIODIC ? i : (i < 0 ? 0 : (i >= n - 1 ? n - 2 : i));
+}
+
+// Transverse node coordinate: slab x_j = (j - (nx-1)/2) delta; axisymmetric
+// r_j = (j + 1/2) delta, so that the axis is the face below row 0 (ghost row
+// -1 is the mirror image of row 0) and 1/r stays finite on every node.
+__device__ __forceinline__ double node_x(double j, int nx, double delta, bool axi)
+{
+    return axi ? (j + 0.5) * delta : (j - 0.5 * (nx - 1)) * delta;
 }
 
 // ---------------------------------------------------------------------------

@@ -33,6 +33,7 @@ struct StepArgs {
     double delta, dt, inv2d, omega, lam, mu, a_lec, two_over_d;
     int dcode;                   // 1, 3 or 0 (general D)
     int do_pull, do_maxwell, lag_init;
+    int axi;                     // 2D local equilibrium: axisymmetric (z, r) geometry
     long step;
     Driver drv;
 };
@@ -74,7 +75,13 @@ __device__ __forceinline__ void collide_all(CT (*s)[Lattice<DIM>::Q], const doub
 // lx, lx + TX/CPT, ...: every thread issues the loads of all its nodes before
 // it waits on any). Recovery runs on the tile plus a one-node ring (LDS), the
 // Yee update on a two-node field halo (LDS).
-template <int CL, class ST, int TZ, int TX, int CPT>
+// AXI (local equilibrium only): axisymmetric (z, r) geometry of Sec. 2.2 and
+// App. A. x is r, node row j sits at r_j = (j + 1/2) delta, rows below the
+// axis are mirror images (populations of the mirrored direction, the odd
+// scalar A_r negated), every advected scalar gets the source -u_r A / r, and
+// the E_z update takes the cylindrical curl (1/r) d_r (r B_phi); E_r and
+// B_phi vanish on the axis.
+template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false>
 __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 {
     using L = Lattice<2>;
@@ -88,6 +95,7 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
     constexpr int NG = CL == LEC ? 1 : 7;    // gradient quantities
     constexpr int NRING = 2 * RZ + 2 * TX;
     static_assert(TX % CPT == 0, "tile rows must split evenly over a thread's nodes");
+    static_assert(!AXI || CL == LEC, "axisymmetric geometry: local-equilibrium closure only");
 
     __shared__ double s_ez[FX][FZ], s_ex[FX][FZ], s_by[FX][FZ], s_bn[FX][FZ];
     __shared__ double s_jz[RX][RZ], s_jx[RX][RZ];
@@ -116,20 +124,38 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 #pragma unroll
     for (int k = 0; k < K; ++k) aref[k] = a.aref[k];
 
-    // source node of direction q: (gx - e_x, gz - e_z) when streaming
+    // source node of direction q: (gx - e_x, gz - e_z) when streaming. AXI:
+    // a source row -1 - m below the axis is the image of row m, whose
+    // direction mx(q) carries f_q there, with A_r (the last scalar) negated;
+    // this also makes the ghost ring row -1 the image of row 0.
     auto load = [&](int gz, int gx, CT (*s)[Q]) {
         const int sh = a.do_pull ? 1 : 0;
         int zs[3], xs[3];
+        bool rf[3];
 #pragma unroll
         for (int e = -1; e <= 1; ++e) {
+            int sx = gx - sh * e;
+            rf[e + 1] = AXI && sx < 0;
+            if (AXI && sx < 0) sx = -1 - sx;
             zs[e + 1] = fix_node(gz - sh * e, nz, bcz);
-            xs[e + 1] = fix_node(gx - sh * e, nx, bcx) * nz;
+            xs[e + 1] = fix_node(sx, nx, bcx) * nz;
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int c = xs[L::ex(q) + 1] + zs[L::ez(q) + 1];
+            if constexpr (AXI) {
+                const bool m = rf[L::ex(q) + 1];
+                const int qs = m ? L::mx(q) : q;
 #pragma unroll
-            for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
+                for (int k = 0; k < K; ++k) {
+                    const CT v = Store<ST>::ld(src + (size_t)(k * Q + qs) * nc, c);
+                    // deviation storage: f = s + w A_ref, and w is the same for q and mx(q)
+                    s[k][q] = (k == K - 1 && m) ? (CT)(-v - (CT)(2.0 * L::w(q) * aref[k])) : v;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
+            }
         }
     };
     // zeroth moments in the storage type, promoted to FP64 (eq. disc-moments-ade)
@@ -272,8 +298,17 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
                 if (fz <= FZ - 3) {  // E_z at (z_{gzz+1/2}, x_gxx)
                     const double jz = 0.5 * (s_jz[rxn(gxx)][rzn(gzz)] + s_jz[rxn(gxx)][rzn(gzz + 1)]);
                     const double jb = -driver_density<2>(a.drv, (gzz + 0.5) * a.delta,
-                                                         (gxx - 0.5 * (nx - 1)) * a.delta, th);
-                    const double cz = (s_by[fxs(gxx)][fzs(gzz)] - s_by[fxs(gxx - 1)][fzs(gzz)]) * id;
+                                                         node_x(gxx, nx, a.delta, AXI), th);
+                    double cz;
+                    if constexpr (AXI) {
+                        // (1/r) d_r (r B_phi) at r_j from r_{j+1/2} = (j+1) delta and
+                        // r_{j-1/2} = j delta (the axis for j = 0); rows below the
+                        // axis are never read
+                        const double bm = gxx > 0 ? s_by[fxs(gxx - 1)][fzs(gzz)] : 0.0;
+                        cz = ((gxx + 1.0) * s_by[fxs(gxx)][fzs(gzz)] - gxx * bm) / ((gxx + 0.5) * a.delta);
+                    } else {
+                        cz = (s_by[fxs(gxx)][fzs(gzz)] - s_by[fxs(gxx - 1)][fzs(gzz)]) * id;
+                    }
                     s_ez[fx][fz] = s_ez[fx][fz] + dt * (cz - jz - jb);
                 }
             }
@@ -306,9 +341,15 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
             const int lx = lxb + r * XS, gx = x0 + lx;
             if (!(gz < nz && gx < nx)) continue;
             const double Ez = 0.5 * (s_ez[fxn(gx)][fzs(gz - 1)] + s_ez[fxn(gx)][fzs(gz)]);
-            const double Ex = 0.5 * (s_ex[fxs(gx - 1)][fzn(gz)] + s_ex[fxs(gx)][fzn(gz)]);
-            const double By = 0.25 * (s_bn[fxs(gx)][fzs(gz)] + s_bn[fxs(gx)][fzs(gz - 1)] +
-                                      s_bn[fxs(gx - 1)][fzs(gz)] + s_bn[fxs(gx - 1)][fzs(gz - 1)]);
+            double Ex, By;
+            if (AXI && gx == 0) {  // E_r and B_phi are zero on the axis r_{-1/2}
+                Ex = 0.5 * s_ex[fxs(gx)][fzn(gz)];
+                By = 0.25 * (s_bn[fxs(gx)][fzs(gz)] + s_bn[fxs(gx)][fzs(gz - 1)]);
+            } else {
+                Ex = 0.5 * (s_ex[fxs(gx - 1)][fzn(gz)] + s_ex[fxs(gx)][fzn(gz)]);
+                By = 0.25 * (s_bn[fxs(gx)][fzs(gz)] + s_bn[fxs(gx)][fzs(gz - 1)] +
+                             s_bn[fxs(gx - 1)][fzs(gz)] + s_bn[fxs(gx - 1)][fzs(gz - 1)]);
+            }
             const int rzc = lz + 1, rxc = lx + 1;
             const int rzp = rzn(gz + 1), rzm = rzn(gz - 1), rxp = rxn(gx + 1), rxm = rxn(gx - 1);
             auto Dz = [&](int g) { return (s_g[g][rxc][rzp] - s_g[g][rxc][rzm]) * a.inv2d; };
@@ -321,6 +362,13 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
                 F[0] = 0.0;
                 F[1] = -a.mu * Dz(0) - n * (Ez + vx * By);
                 F[2] = -a.mu * Dx(0) - n * (Ex - vz * By);
+                if constexpr (AXI) {
+                    // App. A: the cylindrical part of the divergence, -u_r A_k / r
+                    const double ir = 1.0 / ((gx + 0.5) * a.delta);
+                    F[0] -= vx * n * ir;
+                    F[1] -= vx * A[r][1] * ir;
+                    F[2] -= vx * A[r][2] * ir;
+                }
             } else {
                 // App. A warm-closure right-hand sides, Cartesian slab (r -> x, phi -> y)
                 const double th0z = s_g[0][rxc][rzc], th0x = s_g[1][rxc][rzc];
@@ -539,9 +587,14 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
     for (int k = 0; k < K; ++k) {
         typename Store<ST>::ct acc = 0;
         for (int q = 0; q < Q; ++q) {
-            const int sz = gz - L::ez(q), sx = gx - L::ex(q);
+            const int sz = gz - L::ez(q);
+            int sx = gx - L::ex(q), qs = q;
+            // axisymmetric: the row below the axis is the mirror image of row 0
+            const bool m = DIM == 2 && CL == LEC && a.axi && sx < 0;
+            if (m) { sx = -1 - sx; qs = Lattice<2>::mx(q); }
             const int c = fix_node(sx, a.nx, a.bcx) * a.nz + fix_node(sz, a.nz, a.bcz);
-            const typename Store<ST>::ct v = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
+            typename Store<ST>::ct v = Store<ST>::ld(src + (size_t)(k * Q + qs) * nc, c);
+            if (m && k == K - 1) v = -v - (typename Store<ST>::ct)(2.0 * L::w(q) * a.aref[k]);
             Store<ST>::st(dst + (size_t)(k * Q + q) * nc, idx, v);
             acc += v;
         }
@@ -583,7 +636,8 @@ static __global__ void k_finish_b2d(StepArgs a)
     a.by_out[idx] = b1 - hdt * curl;
 }
 
-// Pass 3 (2D): E^n = E^{n-1} + dt (curl B^{n-1/2} - J^n - J_b^{n-1/2}).
+// Pass 3 (2D): E^n = E^{n-1} + dt (curl B^{n-1/2} - J^n - J_b^{n-1/2});
+// axisymmetric: the E_z curl is (1/r) d_r (r B_phi).
 static __global__ void k_finish_e2d(StepArgs a, const double *jz, const double *jx)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -598,8 +652,9 @@ static __global__ void k_finish_e2d(StepArgs a, const double *jz, const double *
     const double cx = -(BY(j, i) - BY(j, i - 1)) * id;
     a.ex_out[idx] = a.ex_in[idx] + dt * (cx - jxe);
     const double jze = 0.5 * (JN(jz, j, i) + JN(jz, j, i + 1));
-    const double jb = -driver_density<2>(a.drv, (i + 0.5) * a.delta, (j - 0.5 * (nx - 1)) * a.delta, th);
-    const double cz = (BY(j, i) - BY(j - 1, i)) * id;
+    const double jb = -driver_density<2>(a.drv, (i + 0.5) * a.delta, node_x(j, nx, a.delta, a.axi), th);
+    const double cz = a.axi ? ((j + 1.0) * BY(j, i) - (j > 0 ? j * BY(j - 1, i) : 0.0)) / ((j + 0.5) * a.delta)
+                            : (BY(j, i) - BY(j - 1, i)) * id;
     a.ez_out[idx] = a.ez_in[idx] + dt * (cz - jze - jb);
 }
 
@@ -719,8 +774,11 @@ __global__ void k_read_field(StepArgs a, int which, int at_nodes, double *out)
         v = which == 0 ? EZ(j, i) : (which == 1 ? EX(j, i) : BH(j, i));
     } else {
         const double ez = 0.5 * (EZ(j, i - 1) + EZ(j, i));
-        const double ex = 0.5 * (EX(j - 1, i) + EX(j, i));
-        const double by = 0.25 * (BN(j, i) + BN(j, i - 1) + BN(j - 1, i) + BN(j - 1, i - 1));
+        // axisymmetric row 0: E_r and B_phi vanish on the axis below it
+        const bool ax = a.axi && j == 0;
+        const double ex = ax ? 0.5 * EX(j, i) : 0.5 * (EX(j - 1, i) + EX(j, i));
+        const double by = ax ? 0.25 * (BN(j, i) + BN(j, i - 1))
+                             : 0.25 * (BN(j, i) + BN(j, i - 1) + BN(j - 1, i) + BN(j - 1, i - 1));
         v = which == 0 ? ez : (which == 1 ? ex : (which == 2 ? by : ex - by));
     }
     out[idx] = v;
@@ -765,12 +823,16 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, double *part)
         }
         const double uu = uz * uz + ux * ux;
         const double g = 1.0 / sqrt(1.0 - uu);
-        const double dV = DIM == 1 ? a.delta : a.delta * a.delta;
         const int i = idx % a.nz, j = idx / a.nz;
         const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
+        const bool axi = DIM == 2 && a.axi;
+        // axisymmetric: 2 pi r per unit cell area; nodes at r_j, E_r and B_phi at r_{j+1/2}
+        const double dV0 = DIM == 1 ? a.delta : a.delta * a.delta;
+        const double dV = axi ? 2.0 * M_PI * node_x(j, nx, a.delta, true) * dV0 : dV0;
+        const double dVh = axi ? 2.0 * M_PI * node_x(j + 0.5, nx, a.delta, true) * dV0 : dV0;
         double fe, div;
         const double t = a.step * a.dt;
-        const double rho = 1.0 - n - driver_density<DIM>(a.drv, i * a.delta, (j - 0.5 * (nx - 1)) * a.delta, t);
+        const double rho = 1.0 - n - driver_density<DIM>(a.drv, i * a.delta, node_x(j, nx, a.delta, axi), t);
         if (DIM == 1) {
             const double e = a.ez_in[idx];
             fe = 0.5 * e * e * dV;
@@ -778,10 +840,18 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, double *part)
         } else {
             const bool rz = bz == BC_PERIODIC || i < nz - 1, rx = bx == BC_PERIODIC || j < nx - 1;
             const double ez = a.ez_in[idx], ex = a.ex_in[idx], by = a.by_in[idx];
-            fe = ((rz ? 0.5 * ez * ez : 0.0) + (rx ? 0.5 * ex * ex : 0.0) + (rz && rx ? 0.5 * by * by : 0.0)) * dV;
+            if (axi)
+                fe = (rz ? 0.5 * ez * ez : 0.0) * dV + ((rx ? 0.5 * ex * ex : 0.0) + (rz && rx ? 0.5 * by * by : 0.0)) * dVh;
+            else
+                fe = ((rz ? 0.5 * ez * ez : 0.0) + (rx ? 0.5 * ex * ex : 0.0) + (rz && rx ? 0.5 * by * by : 0.0)) * dV;
             auto EZ = [&](int jj, int ii) { return a.ez_in[(size_t)fix_node(jj, nx, bx) * nz + fix_stag(ii, nz, bz)]; };
             auto EX = [&](int jj, int ii) { return a.ex_in[(size_t)fix_stag(jj, nx, bx) * nz + fix_node(ii, nz, bz)]; };
-            div = (EZ(j, i) - EZ(j, i - 1)) / a.delta + (EX(j, i) - EX(j - 1, i)) / a.delta;
+            if (axi) {
+                const double em = j > 0 ? EX(j - 1, i) : 0.0;
+                div = (EZ(j, i) - EZ(j, i - 1)) / a.delta + ((j + 1.0) * EX(j, i) - j * em) / ((j + 0.5) * a.delta);
+            } else {
+                div = (EZ(j, i) - EZ(j, i - 1)) / a.delta + (EX(j, i) - EX(j - 1, i)) / a.delta;
+            }
         }
         const bool bad = !isfinite(n) || !isfinite(uz) || !isfinite(ux) || !isfinite(a.ez_in[idx]) ||
                          (DIM == 2 && (!isfinite(a.ex_in[idx]) || !isfinite(a.by_in[idx])));
@@ -832,7 +902,8 @@ static __global__ __launch_bounds__(256) void k_diag_final(const double *part, i
 // Analytic field of the bunch alone at t = 0 (Sec. 5). 1D: E_z(z) = alpha
 // times the integral of the profile from z to +infinity, evaluated per slice.
 // 2D: E_z = 0, E_x = -g(zeta) sigma_x sqrt(pi/2) erf(x / (sqrt 2 sigma_x)),
-// B_y = E_x taken at t = -dt/2.
+// B_y = E_x taken at t = -dt/2. Axisymmetric: the cylindrical Gauss law
+// (1/r) d_r (r E_r) = -n_b gives E_r = -g(zeta) sigma_r^2 (1 - e^{-r^2/2 sigma_r^2}) / r.
 template <int DIM>
 __global__ void k_init_fields(StepArgs a, double *ez, double *ex, double *by)
 {
@@ -859,9 +930,10 @@ __global__ void k_init_fields(StepArgs a, double *ez, double *ex, double *by)
         ez[idx] = d.alpha * acc;
         return;
     }
-    const double xh = (j + 0.5 - 0.5 * (a.nx - 1)) * a.delta - d.x0;
+    const double xh = node_x(j + 0.5, a.nx, a.delta, a.axi) - d.x0;
     const double sx = d.sigma_x;
-    const double tr = -sx * sqrt(M_PI / 2.0) * erf(xh / (sqrt(2.0) * sx));
+    const double tr = a.axi ? -sx * sx * (1.0 - exp(-xh * xh / (2.0 * sx * sx))) / xh
+                            : -sx * sqrt(M_PI / 2.0) * erf(xh / (sqrt(2.0) * sx));
     const double ze = i * a.delta - d.z0;
     const double zb = (i + 0.5) * a.delta - d.z0 + 0.5 * a.dt;
     ez[idx] = 0.0;

@@ -93,7 +93,17 @@ bool grid_valid(const lbw_grid_desc *g, std::string *why)
     if (g->bc_z != LBW_BC_OPEN && g->bc_z != LBW_BC_PERIODIC) return bad("unknown bc_z");
     if (g->bc_x != LBW_BC_OPEN && g->bc_x != LBW_BC_PERIODIC) return bad("unknown bc_x");
     if (!(g->dvel > 0)) return bad("dvel must be positive");
+    if (g->geom != LBW_GEOM_SLAB && g->geom != LBW_GEOM_AXI) return bad("unknown geometry");
+    if (g->geom == LBW_GEOM_AXI && (g->dims != 2 || g->bc_x != LBW_BC_OPEN))
+        return bad("the axisymmetric geometry is 2D with an open outer radius");
     return true;
+}
+
+// Valid descriptors the library does not implement: the warm closure in the
+// axisymmetric geometry.
+bool grid_supported(const lbw_grid_desc *g)
+{
+    return !(g->geom == LBW_GEOM_AXI && g->closure != LBW_LEC);
 }
 
 Layout make_layout(const lbw_grid_desc *g)
@@ -179,6 +189,7 @@ StepArgs base_args(lbw_sim *s)
     a.a_lec = (1.0 + 0.5 * g.dvel) * s->mu;
     a.two_over_d = 2.0 / g.dvel;
     a.dcode = g.dvel == 1.0 ? 1 : (g.dvel == 3.0 ? 3 : 0);
+    a.axi = g.geom == LBW_GEOM_AXI;
     a.aref = (const double *)(s->ws + s->L.aref);
     a.fallbacks = (unsigned int *)(s->ws + s->L.fallbacks);
     a.lag = g.closure == LBW_WARMC ? (double *)(s->ws + s->L.lag) : nullptr;
@@ -199,14 +210,14 @@ void set_io(lbw_sim *s, StepArgs &a)
     a.by_out = (double *)(s->ws + s->L.fld[1 - s->fcur][2]);
 }
 
-template <int DIM, int CL, class ST> struct Impl {
+template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
     static void step(const StepArgs &a, hipStream_t st)
     {
         if constexpr (DIM == 2) {
             // one-dimensional grid: the kernel maps blocks to tiles XCD by XCD
             using T = Tile2<CL, ST>;
             dim3 grid(((a.nz + T::TZ - 1) / T::TZ) * ((a.nx + T::TX - 1) / T::TX));
-            hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT>), grid,
+            hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI>), grid,
                                dim3(T::TZ * T::TX / T::CPT), 0, st, a);
         } else {
             dim3 grid((a.nz + TZ1 - 1) / TZ1);
@@ -285,9 +296,9 @@ struct Ops {
     void (*diag)(const StepArgs &, double *, int, double *, hipStream_t);
 };
 
-template <int DIM, int CL, class ST> Ops ops_of()
+template <int DIM, int CL, class ST, bool AXI = false> Ops ops_of()
 {
-    using I = Impl<DIM, CL, ST>;
+    using I = Impl<DIM, CL, ST, AXI>;
     return Ops{&I::step, &I::persist_grid, &I::step_persist, &I::finish, &I::init_pops, &I::read_moment, &I::diag};
 }
 
@@ -300,6 +311,11 @@ template <int DIM, int CL> Ops ops_st(int storage)
 
 Ops ops_for(const lbw_grid_desc &g)
 {
+    if (g.geom == LBW_GEOM_AXI) {  // 2D local equilibrium (grid_supported)
+        if (g.storage == LBW_FP64) return ops_of<2, LEC, double, true>();
+        if (g.storage == LBW_FP32) return ops_of<2, LEC, float, true>();
+        return ops_of<2, LEC, __half, true>();
+    }
     if (g.dims == 1) return g.closure == LBW_LEC ? ops_st<1, LEC>(g.storage) : ops_st<1, WARMC>(g.storage);
     return g.closure == LBW_LEC ? ops_st<2, LEC>(g.storage) : ops_st<2, WARMC>(g.storage);
 }
@@ -335,7 +351,7 @@ extern "C" {
 
 size_t lbw_workspace_bytes(const lbw_grid_desc *grid)
 {
-    if (!grid_valid(grid, nullptr)) return 0;
+    if (!grid_valid(grid, nullptr) || !grid_supported(grid)) return 0;
     return make_layout(grid).total;
 }
 
@@ -348,6 +364,7 @@ lbw_status lbw_create(const lbw_grid_desc *grid, void *ws, size_t ws_bytes, void
     *out = nullptr;
     std::string why;
     if (!grid_valid(grid, &why)) return LBW_ERR_ARG;
+    if (!grid_supported(grid)) return LBW_ERR_UNSUPPORTED;
     if (!(grid->tau_tilde > 0.5)) return LBW_ERR_UNSTABLE;
     if (grid->dt > grid->delta / std::sqrt((double)grid->dims) * (1.0 + 1e-12)) return LBW_ERR_UNSTABLE;
     const Layout L = make_layout(grid);
@@ -549,6 +566,8 @@ lbw_status lbw_init_driver(lbw_sim *s, const lbw_driver_desc *d, int init_fields
     if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
     if (d->alpha != 0.0 && (!(d->sigma_z > 0) || (s->g.dims == 2 && !(d->sigma_x > 0))))
         return fail(s, LBW_ERR_ARG, "bunch widths must be positive");
+    if (s->g.geom == LBW_GEOM_AXI && d->x0 != 0.0)
+        return fail(s, LBW_ERR_ARG, "the axisymmetric driver sits on the axis (x0 = 0)");
     if (d->nslices < 0 || d->nslices > MAX_SLICES || (d->nslices > 0 && !d->slice_w) ||
         (d->nslices > 0 && !(d->slice_zmax > d->slice_zmin)))
         return fail(s, LBW_ERR_ARG, "invalid slice description");
@@ -898,8 +917,8 @@ static lbw_status adj_args(lbw_sim *s, double *adj, double *grad, void *scratch,
 {
     if (!s || !adj || !grad || !scratch) return fail(s, LBW_ERR_ARG, "NULL argument");
     if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
-    if (s->g.dims != 2 || s->g.closure != LBW_LEC)
-        return fail(s, LBW_ERR_UNSUPPORTED, "the adjoint covers the 2D local-equilibrium closure");
+    if (s->g.dims != 2 || s->g.closure != LBW_LEC || s->g.geom != LBW_GEOM_SLAB)
+        return fail(s, LBW_ERR_UNSUPPORTED, "the adjoint covers the 2D local-equilibrium closure in slab geometry");
     if (s->drv.nslices <= 0) return fail(s, LBW_ERR_STATE, "the driver has no slices to differentiate");
     if (s->drv.nslices > 1024) return fail(s, LBW_ERR_UNSUPPORTED, "the adjoint handles at most 1024 slices");
     if (((uintptr_t)scratch % ALIGN) != 0) return fail(s, LBW_ERR_ARG, "scratch must be 256-byte aligned");

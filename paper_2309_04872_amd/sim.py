@@ -24,13 +24,15 @@ class Sim:
 
     Parameters mirror ``lbw_grid_desc``: ``closure`` in {'lec', 'warmc'},
     ``storage`` in {'fp64', 'fp32', 'fp16dev'}, ``bc_z``/``bc_x`` in
-    {'open', 'periodic'}. ``dt`` defaults to delta / 10 and ``tau_tilde`` to
-    0.52 (1D) / 0.53 (2D), the paper's choices (Sec. 5).
+    {'open', 'periodic'}, ``geom`` in {'slab', 'axi'} (2D: Cartesian (z, x)
+    or the axisymmetric (z, r) geometry of App. A, where x runs over
+    r_j = (j + 1/2) delta). ``dt`` defaults to delta / 10 and ``tau_tilde``
+    to 0.52 (1D) / 0.53 (2D), the paper's choices (Sec. 5).
     """
 
     def __init__(self, dims, nz, nx=1, delta=2 * np.pi / 128, dt=None, tau_tilde=None,
                  closure="lec", dvel=None, storage="fp64", bc_z="open", bc_x="open",
-                 device="cuda:0", stream=None):
+                 geom="slab", device="cuda:0", stream=None):
         import torch
 
         self._lib = _lib.load()
@@ -45,10 +47,14 @@ class Sim:
         self.ncell = nx * nz
         self.closure = closure
         self.grid = _lib.GridDesc(dims, nz, nx, delta, dt, tau_tilde, _lib.CLOSURES[closure],
-                                  float(dvel), _lib.STORAGE[storage], _lib.BCS[bc_z], _lib.BCS[bc_x])
+                                  float(dvel), _lib.STORAGE[storage], _lib.BCS[bc_z], _lib.BCS[bc_x],
+                                  _lib.GEOMS[geom])
+        self.geom = geom
         nbytes = self._lib.lbw_workspace_bytes(ctypes.byref(self.grid))
         if nbytes == 0:
-            raise LbwError(-1, "invalid grid descriptor")
+            h = ctypes.c_void_p()
+            rc = self._lib.lbw_create(ctypes.byref(self.grid), None, 0, None, ctypes.byref(h))
+            raise LbwError(rc if rc != 0 else -1, "invalid or unsupported grid descriptor")
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if stream is None:

@@ -55,6 +55,14 @@ WORKLOADS = {
     "wake2d_warmc": dict(
         dims=2, nz=4096, nx=1024, delta=LAMBDA_P / 64, closure="warmc", dvel=3.0, storage="fp64",
         mu=5e-2, noise=0.0, seed=0, alpha=2.0, sigma_z=1.0, sigma_x=0.5, steps=8000),
+    # The paper's 3D3V production case (Sec. 5, Fig. 4 and 5): axisymmetric
+    # (z, r), L_z = 30, L_r = 6 at delta = 0.01 (3000 x 600 nodes), 30 000
+    # steps, mu = 0.04 (20 keV), Q~ = 0.5 with sigma_z = sigma_r = 25 um at
+    # n_i = 1e16 cm^-3 (0.4704 / k_p, rms convention).
+    "wake_axi_lec": dict(
+        dims=2, geom="axi", nz=3000, nx=600, delta=0.01, closure="lec", dvel=3.0, storage="fp64",
+        mu=0.04, noise=0.0, seed=0, alpha=None, q_tilde=0.5, sigma_z=0.4704, sigma_x=0.4704,
+        steps=30000),
     "wake2d_lec_adjoint": dict(
         dims=2, nz=1024, nx=256, delta=LAMBDA_P / 64, closure="lec", dvel=3.0, storage="fp32",
         mu=1e-2, noise=0.0, seed=0, alpha=0.5, sigma_z=1.0, sigma_x=0.5, steps=2000,
@@ -62,9 +70,18 @@ WORKLOADS = {
 }
 
 
+def alpha_of_q_tilde(q_tilde, sigma_z, sigma_r, D=3):
+    """Peak bunch density n_b / n_i for the normalised charge
+    Q~ = (2 pi)^{D/2} sigma_z sigma_r^{D-1} alpha (eq. Qtilde, plasma units)."""
+    return q_tilde / ((2.0 * math.pi) ** (D / 2.0) * sigma_z * sigma_r ** (D - 1))
+
+
 def workload(name, **overrides):
     w = dict(WORKLOADS[name])
     w.update(overrides)
+    w.setdefault("geom", "slab")
+    if w.get("alpha") is None:
+        w["alpha"] = alpha_of_q_tilde(w["q_tilde"], w["sigma_z"], w["sigma_x"])
     w["dt"] = 0.1 * w["delta"]
     w["tau_tilde"] = 0.52 if w["dims"] == 1 else 0.53
     w["z0"] = 6.0 * w["sigma_z"]

@@ -6,6 +6,7 @@ from paper_2309_04872_amd.sim import Sim
 
 CL = {"lec": oracle.LEC, "warmc": oracle.WARMC}
 BC = {"open": oracle.OPEN, "periodic": oracle.PERIODIC}
+GEOM = {"slab": oracle.SLAB, "axi": oracle.AXI}
 
 FLUID = ["n", "uz", "ux", "gamma", "n0", "p0", "mz", "mx"]
 WARM = ["lambda", "thzz", "thxx", "thyy", "thxz", "ppar"]
@@ -14,16 +15,16 @@ FIELDS = ["ez", "ex", "by"]
 
 def make_pair(dims, nz, nx=1, delta=2 * np.pi / 128, closure="lec", dvel=None, storage="fp64",
               bc_z="open", bc_x="open", mu=1e-2, n=None, uz=None, ux=None, driver=None,
-              tau_tilde=None, dt=None, oracle_only=False):
+              tau_tilde=None, dt=None, oracle_only=False, geom="slab"):
     kw = dict(delta=delta, dt=dt, tau_tilde=tau_tilde)
     o = oracle.Oracle(dims, nz, nx, closure=CL[closure], dvel=dvel, bc_z=BC[bc_z], bc_x=BC[bc_x],
-                      mu=mu, **{k: v for k, v in kw.items() if v is not None},
+                      mu=mu, geom=GEOM[geom], **{k: v for k, v in kw.items() if v is not None},
                       **(_oracle_driver(driver) if driver else {}))
     o.init(n=n, uz=uz, ux=ux, fields_from_driver=bool(driver))
     if oracle_only:
         return None, o
     s = Sim(dims, nz, nx, closure=closure, dvel=dvel, storage=storage, bc_z=bc_z, bc_x=bc_x,
-            **{k: v for k, v in kw.items() if v is not None})
+            geom=geom, **{k: v for k, v in kw.items() if v is not None})
     s.init_plasma(mu, n=n, uz=uz, ux=ux)
     if driver:
         s.init_driver(**driver, init_fields=True)
