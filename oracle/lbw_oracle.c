@@ -414,6 +414,14 @@ static double ddx(const orc_state *s, const double *X, int j, int i)
     if (s->p.dims == 1) return 0.0;
     return (X[cell(s, j + 1, i)] - X[cell(s, j - 1, i)]) / (2.0 * s->p.delta);
 }
+/* Radial derivative of a quantity that changes sign under r -> -r: in the
+ * axisymmetric geometry the row below the axis holds -X of row 0. */
+static double ddx_odd(const orc_state *s, const double *X, int j, int i)
+{
+    if (s->p.geom == ORC_GEOM_AXI && j == 0)
+        return (X[cell(s, 1, i)] + X[cell(s, 0, i)]) / (2.0 * s->p.delta);
+    return ddx(s, X, j, i);
+}
 
 /* S5: forcing terms. */
 static void forces(orc_state *s)
@@ -463,11 +471,12 @@ static void forces(orc_state *s)
                 double dt_th0x = (th0x - G[G_TH0X * nc + c]) / dt;
                 double dt_luz = (luz - G[G_LUZ * nc + c]) / dt;
                 double dt_lux = (lux - G[G_LUX * nc + c]) / dt;
-                double dz_th0z = ddz(s, RR(R_TH0Z), j, i), dx_th0x = ddx(s, RR(R_TH0X), j, i);
-                double dz_thzz = ddz(s, RR(R_THZZ), j, i), dx_thxz = ddx(s, RR(R_THXZ), j, i);
+                /* theta^{0x}, theta^{xz} and lambda u_x are odd in x (r) */
+                double dz_th0z = ddz(s, RR(R_TH0Z), j, i), dx_th0x = ddx_odd(s, RR(R_TH0X), j, i);
+                double dz_thzz = ddz(s, RR(R_THZZ), j, i), dx_thxz = ddx_odd(s, RR(R_THXZ), j, i);
                 double dz_thxz = ddz(s, RR(R_THXZ), j, i), dx_thxx = ddx(s, RR(R_THXX), j, i);
                 double dz_luz = ddz(s, RR(R_LUZ), j, i), dx_luz = ddx(s, RR(R_LUZ), j, i);
-                double dz_lux = ddz(s, RR(R_LUX), j, i), dx_lux = ddx(s, RR(R_LUX), j, i);
+                double dz_lux = ddz(s, RR(R_LUX), j, i), dx_lux = ddx_odd(s, RR(R_LUX), j, i);
                 if (s->p.dims == 1) {
                     F[W1_NL * nc + c] = -dt_th00 - dz_th0z - n * (Ez * uz);
                     F[W1_NLUZ * nc + c] = -dt_th0z - dz_thzz - n * Ez;
@@ -485,6 +494,27 @@ static void forces(orc_state *s)
                     F[W_THXZ * nc + c] = -th0z * dt_lux - th0x * dt_luz - thxz * dx_lux -
                                          thxx * dx_luz - thzz * dz_lux - thxz * dz_luz -
                                          (Ex * th0z + Ez * th0x + By * (thxx - thzz));
+                    if (s->p.geom == ORC_GEOM_AXI) {
+                        /* App. A, WARMC: -u_r A / r for every advected scalar,
+                         * the cylindrical parts of the divergences of theta^{0j}
+                         * and theta^{ij} (-theta^{0r}/r, -(theta^{rr} -
+                         * theta^{phiphi})/r, -theta^{rz}/r), and a total of
+                         * -3 lambda theta^{phiphi} u_r / r for theta^{phiphi} */
+                        double ir = 1.0 / node_x(s, j), A[8];
+                        for (int k = 0; k < 8; ++k) {
+                            A[k] = 0.0;
+                            for (int q = 0; q < s->Q; ++q) A[k] += s->f[(k * s->Q + q) * nc + c];
+                        }
+                        double thyy = RR(R_THYY)[c];
+                        F[W_N * nc + c] -= ux * A[W_N] * ir;
+                        F[W_NL * nc + c] -= ux * A[W_NL] * ir + th0x * ir;
+                        F[W_NLUZ * nc + c] -= ux * A[W_NLUZ] * ir + thxz * ir;
+                        F[W_NLUX * nc + c] -= ux * A[W_NLUX] * ir + (thxx - thyy) * ir;
+                        F[W_THZZ * nc + c] -= ux * A[W_THZZ] * ir;
+                        F[W_THXX * nc + c] -= ux * A[W_THXX] * ir;
+                        F[W_THYY * nc + c] -= 3.0 * ux * A[W_THYY] * ir;
+                        F[W_THXZ * nc + c] -= ux * A[W_THXZ] * ir;
+                    }
                 }
             }
         }
@@ -519,8 +549,8 @@ static void collide_stream(orc_state *s)
      * Axisymmetric geometry: the axis lies midway between row 0 and the
      * ghost row -1, and the ghost holds the mirror image of row 0: the
      * populations of the mirrored direction (eq. reflective-bc), with the
-     * sign reversed for the one scalar that is odd under r -> -r (the radial
-     * momentum A_r). This is our reading of the axis rule of Sec. 2.2 for
+     * sign reversed for the scalars that are odd under r -> -r (the radial
+     * momentum A_r; n lambda u_r and lambda theta^{rz}). This is our reading of the axis rule of Sec. 2.2 for
      * this node layout: a plain copy (eq. open-bc) for the even scalars
      * would let mass cross the axis, which the cylindrical divergence of
      * App. A does not allow. */
@@ -535,7 +565,10 @@ static void collide_stream(orc_state *s)
                 for (int k = 0; k < K; ++k) {
                     int qs = q;
                     double sg = 1.0;
-                    if (axi && sj < 0) { qs = s->mirror_x[q]; if (k == L_AX) sg = -1.0; }
+                    if (axi && sj < 0) {
+                        qs = s->mirror_x[q];
+                        if (s->p.closure == ORC_LEC ? k == L_AX : (k == W_NLUX || k == W_THXZ)) sg = -1.0;
+                    }
                     f[(k * Q + q) * nc + c] = sg * fs[(k * Q + qs) * nc + src];
                 }
             }
@@ -624,7 +657,7 @@ orc_state *orc_create(const orc_params *p)
     if (!(p->tau_tilde > 0.5) || !(p->dt > 0) || !(p->delta > 0)) return NULL;
     if (p->geom != ORC_GEOM_SLAB && p->geom != ORC_GEOM_AXI) return NULL;
     if (p->geom == ORC_GEOM_AXI &&
-        (p->dims != 2 || p->closure != ORC_LEC || p->bc_x != ORC_BC_OPEN || p->x0 != 0.0))
+        (p->dims != 2 || p->bc_x != ORC_BC_OPEN || p->x0 != 0.0))
         return NULL;
     orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
     s->p = *p;

@@ -64,8 +64,8 @@ typedef struct {
     double slice_zmin, slice_zmax; /* slice span in zeta = z - z0 - t */
     const double *slice_w; /* nslices weights (copied) */
     /* ORC_GEOM_SLAB: Cartesian (z, x). ORC_GEOM_AXI: axisymmetric (z, r), the
-     * 3D3V geometry of Sec. 2.2 and App. A (2D, local-equilibrium closure,
-     * bc_x open at the outer radius; x0 must be 0). Node j sits at
+     * 3D3V geometry of Sec. 2.2 and App. A (2D, either closure, bc_x open at
+     * the outer radius; x0 must be 0; x, y read as r, phi). Node j sits at
      * r_j = (j + 1/2) delta; the ghost row j = -1 mirrors the axis. */
     int geom;
 } orc_params;
