@@ -64,12 +64,15 @@ typedef enum { LBW_BC_OPEN = 0, LBW_BC_PERIODIC = 1 } lbw_bc;
 
 /* Transverse geometry of a 2D grid. SLAB: Cartesian (z, x), node row j at
  * x_j = (j - (nx-1)/2) delta. AXI: the axisymmetric (z, r) geometry of
- * Sec. 2.2 and App. A (local-equilibrium closure, open outer radius): node
- * row j at r_j = (j + 1/2) delta, the cylindrical part of every divergence
- * as a source -u_r A / r, the E_z update with (1/r) d_r (r B_phi), E_r and
- * B_phi zero on the axis; below the axis the populations are the mirror
- * image of row 0 (mirrored directions, eq. reflective-bc, with the radial
- * momentum A_r negated). The x arrays then run over r. */
+ * Sec. 2.2 and App. A (both closures, open outer radius): node row j at
+ * r_j = (j + 1/2) delta, the cylindrical parts of the divergences as sources
+ * (-u_r A / r for every advected scalar; for the warm closure also
+ * -theta^{0r}/r, -(theta^{rr} - theta^{phiphi})/r, -theta^{rz}/r and the
+ * theta^{phiphi} term of App. A), the E_z update with (1/r) d_r (r B_phi),
+ * E_r and B_phi zero on the axis; below the axis the populations are the
+ * mirror image of row 0 (mirrored directions, eq. reflective-bc, with the
+ * scalars odd in r negated: A_r; n lambda u_r and lambda theta^{rz}). The x
+ * arrays then run over r, the y components over phi. */
 typedef enum { LBW_GEOM_SLAB = 0, LBW_GEOM_AXI = 1 } lbw_geom;
 
 /* Fluid observables for lbw_read_moment (one value per node). */
@@ -134,8 +137,7 @@ typedef struct lbw_sim lbw_sim;
 size_t lbw_workspace_bytes(const lbw_grid_desc *grid);
 
 /* Validate the grid (tau~ > 1/2, Courant dt <= delta / sqrt(dims)) and bind
- * the caller's workspace and stream (hipStream_t, NULL = default stream).
- * LBW_ERR_UNSUPPORTED for the warm closure in the axisymmetric geometry. */
+ * the caller's workspace and stream (hipStream_t, NULL = default stream). */
 lbw_status lbw_create(const lbw_grid_desc *grid, void *device_workspace,
                       size_t workspace_bytes, void *hip_stream, lbw_sim **out);
 

@@ -38,6 +38,14 @@ struct StepArgs {
     Driver drv;
 };
 
+// Advected scalars that change sign under r -> -r in the axisymmetric
+// geometry: the radial momentum A_r (LEC), n lambda u_r and lambda theta^{rz}
+// (WARMC, 2D order of NScal).
+template <int CL> __device__ __forceinline__ constexpr bool odd_in_r(int k)
+{
+    return CL == LEC ? k == 2 : (k == 3 || k == 7);
+}
+
 // ---------------------------------------------------------------------------
 // Collision of all scalars in deviation form (A_ref = 0 gives the plain form):
 // s*_{k,q} = (1 - omega) s_{k,q} + w_q (omega dA_k + dt F_k + omega A_k P_q),
@@ -75,12 +83,14 @@ __device__ __forceinline__ void collide_all(CT (*s)[Lattice<DIM>::Q], const doub
 // lx, lx + TX/CPT, ...: every thread issues the loads of all its nodes before
 // it waits on any). Recovery runs on the tile plus a one-node ring (LDS), the
 // Yee update on a two-node field halo (LDS).
-// AXI (local equilibrium only): axisymmetric (z, r) geometry of Sec. 2.2 and
-// App. A. x is r, node row j sits at r_j = (j + 1/2) delta, rows below the
-// axis are mirror images (populations of the mirrored direction, the odd
-// scalar A_r negated), every advected scalar gets the source -u_r A / r, and
-// the E_z update takes the cylindrical curl (1/r) d_r (r B_phi); E_r and
-// B_phi vanish on the axis.
+// AXI: axisymmetric (z, r) geometry of Sec. 2.2 and App. A. x is r, node
+// row j sits at r_j = (j + 1/2) delta, rows below the axis are mirror images
+// (populations of the mirrored direction, the scalars odd in r negated; the
+// ring row -1 then holds the image's recovered values, which radial
+// differences at row 0 read), every advected scalar gets the source
+// -u_r A / r plus, for the warm closure, the cylindrical parts of the tensor
+// divergences, and the E_z update takes the cylindrical curl
+// (1/r) d_r (r B_phi); E_r and B_phi vanish on the axis.
 template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false>
 __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 {
@@ -95,7 +105,6 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
     constexpr int NG = CL == LEC ? 1 : 7;    // gradient quantities
     constexpr int NRING = 2 * RZ + 2 * TX;
     static_assert(TX % CPT == 0, "tile rows must split evenly over a thread's nodes");
-    static_assert(!AXI || CL == LEC, "axisymmetric geometry: local-equilibrium closure only");
 
     __shared__ double s_ez[FX][FZ], s_ex[FX][FZ], s_by[FX][FZ], s_bn[FX][FZ];
     __shared__ double s_jz[RX][RZ], s_jx[RX][RZ];
@@ -126,7 +135,7 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 
     // source node of direction q: (gx - e_x, gz - e_z) when streaming. AXI:
     // a source row -1 - m below the axis is the image of row m, whose
-    // direction mx(q) carries f_q there, with A_r (the last scalar) negated;
+    // direction mx(q) carries f_q there, with the scalars odd in r negated;
     // this also makes the ghost ring row -1 the image of row 0.
     auto load = [&](int gz, int gx, CT (*s)[Q]) {
         const int sh = a.do_pull ? 1 : 0;
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
                 for (int k = 0; k < K; ++k) {
                     const CT v = Store<ST>::ld(src + (size_t)(k * Q + qs) * nc, c);
                     // deviation storage: f = s + w A_ref, and w is the same for q and mx(q)
-                    s[k][q] = (k == K - 1 && m) ? (CT)(-v - (CT)(2.0 * L::w(q) * aref[k])) : v;
+                    s[k][q] = (odd_in_r<CL>(k) && m) ? (CT)(-v - (CT)(2.0 * L::w(q) * aref[k])) : v;
                 }
             } else {
 #pragma unroll
@@ -273,7 +282,8 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
         auto fxn = [&](int g) { return (EDGE ? map_node(g, nx, bcx) : g) - (x0 - 2); };
         auto fxs = [&](int g) { return (EDGE ? map_stag(g, nx, bcx) : g) - (x0 - 2); };
         auto rzn = [&](int g) { return (EDGE ? map_node(g, nz, bcz) : g) - (z0 - 1); };
-        auto rxn = [&](int g) { return (EDGE ? map_node(g, nx, bcx) : g) - (x0 - 1); };
+        // AXI: row -1 of the recovery ring is the mirror image of row 0
+        auto rxn = [&](int g) { return (EDGE && !(AXI && g < 0) ? map_node(g, nx, bcx) : g) - (x0 - 1); };
         const double dt = a.dt, hdt = 0.5 * a.dt, id = 1.0 / a.delta;
         // ---- 4. finish the Yee update of the previous step with J^n
         if (a.do_maxwell) {
@@ -400,6 +410,21 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
                 F[6] = 0.0;
                 F[7] = -th0z * dtlux - th0x * dtluz - thxz * Dx(6) - thxx * Dx(5) - thzz * Dz(6) -
                        thxz * Dz(5) - (Ex * th0z + Ez * th0x + By * (thxx - thzz));
+                if constexpr (AXI) {
+                    // App. A, warm closure: -u_r A_k / r for every scalar, the
+                    // cylindrical parts of the divergences of theta^{0j} and
+                    // theta^{ij}, and -3 lambda theta^{phiphi} u_r / r in total
+                    const double ir = 1.0 / ((gx + 0.5) * a.delta);
+                    const double thyy = A[r][6] / (A[r][1] / n);
+                    F[0] -= vx * n * ir;
+                    F[1] -= vx * A[r][1] * ir + th0x * ir;
+                    F[2] -= vx * A[r][2] * ir + thxz * ir;
+                    F[3] -= vx * A[r][3] * ir + (thxx - thyy) * ir;
+                    F[4] -= vx * A[r][4] * ir;
+                    F[5] -= vx * A[r][5] * ir;
+                    F[6] -= 3.0 * vx * A[r][6] * ir;
+                    F[7] -= vx * A[r][7] * ir;
+                }
             }
             collide_all<2, K, CT>(s[r], A[r], aref, F, vz, vx, a.lam, a.omega, dt);
 #pragma unroll
@@ -590,11 +615,11 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
             const int sz = gz - L::ez(q);
             int sx = gx - L::ex(q), qs = q;
             // axisymmetric: the row below the axis is the mirror image of row 0
-            const bool m = DIM == 2 && CL == LEC && a.axi && sx < 0;
+            const bool m = DIM == 2 && a.axi && sx < 0;
             if (m) { sx = -1 - sx; qs = Lattice<2>::mx(q); }
             const int c = fix_node(sx, a.nx, a.bcx) * a.nz + fix_node(sz, a.nz, a.bcz);
             typename Store<ST>::ct v = Store<ST>::ld(src + (size_t)(k * Q + qs) * nc, c);
-            if (m && k == K - 1) v = -v - (typename Store<ST>::ct)(2.0 * L::w(q) * a.aref[k]);
+            if (m && odd_in_r<CL>(k)) v = -v - (typename Store<ST>::ct)(2.0 * L::w(q) * a.aref[k]);
             Store<ST>::st(dst + (size_t)(k * Q + q) * nc, idx, v);
             acc += v;
         }

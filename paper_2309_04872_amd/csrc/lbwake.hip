@@ -99,12 +99,8 @@ bool grid_valid(const lbw_grid_desc *g, std::string *why)
     return true;
 }
 
-// Valid descriptors the library does not implement: the warm closure in the
-// axisymmetric geometry.
-bool grid_supported(const lbw_grid_desc *g)
-{
-    return !(g->geom == LBW_GEOM_AXI && g->closure != LBW_LEC);
-}
+// Valid descriptors the library does not implement (none at present).
+bool grid_supported(const lbw_grid_desc *) { return true; }
 
 Layout make_layout(const lbw_grid_desc *g)
 {
@@ -311,10 +307,15 @@ template <int DIM, int CL> Ops ops_st(int storage)
 
 Ops ops_for(const lbw_grid_desc &g)
 {
-    if (g.geom == LBW_GEOM_AXI) {  // 2D local equilibrium (grid_supported)
-        if (g.storage == LBW_FP64) return ops_of<2, LEC, double, true>();
-        if (g.storage == LBW_FP32) return ops_of<2, LEC, float, true>();
-        return ops_of<2, LEC, __half, true>();
+    if (g.geom == LBW_GEOM_AXI) {  // 2D (grid_valid)
+        if (g.closure == LBW_LEC) {
+            if (g.storage == LBW_FP64) return ops_of<2, LEC, double, true>();
+            if (g.storage == LBW_FP32) return ops_of<2, LEC, float, true>();
+            return ops_of<2, LEC, __half, true>();
+        }
+        if (g.storage == LBW_FP64) return ops_of<2, WARMC, double, true>();
+        if (g.storage == LBW_FP32) return ops_of<2, WARMC, float, true>();
+        return ops_of<2, WARMC, __half, true>();
     }
     if (g.dims == 1) return g.closure == LBW_LEC ? ops_st<1, LEC>(g.storage) : ops_st<1, WARMC>(g.storage);
     return g.closure == LBW_LEC ? ops_st<2, LEC>(g.storage) : ops_st<2, WARMC>(g.storage);

@@ -63,6 +63,10 @@ WORKLOADS = {
         dims=2, geom="axi", nz=3000, nx=600, delta=0.01, closure="lec", dvel=3.0, storage="fp64",
         mu=0.04, noise=0.0, seed=0, alpha=None, q_tilde=0.5, sigma_z=0.4704, sigma_x=0.4704,
         steps=30000),
+    "wake_axi_warmc": dict(
+        dims=2, geom="axi", nz=3000, nx=600, delta=0.01, closure="warmc", dvel=3.0, storage="fp64",
+        mu=0.04, noise=0.0, seed=0, alpha=None, q_tilde=0.5, sigma_z=0.4704, sigma_x=0.4704,
+        steps=30000),
     "wake2d_lec_adjoint": dict(
         dims=2, nz=1024, nx=256, delta=LAMBDA_P / 64, closure="lec", dvel=3.0, storage="fp32",
         mu=1e-2, noise=0.0, seed=0, alpha=0.5, sigma_z=1.0, sigma_x=0.5, steps=2000,

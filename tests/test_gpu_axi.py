@@ -1,4 +1,4 @@
-"""Axisymmetric (z, r) local-equilibrium geometry (Sec. 2.2, App. A) on the
+"""Axisymmetric (z, r) geometry (Sec. 2.2, App. A), both closures, on the
 HIP library against the CPU oracle, through the C ABI: small grids spanning
 several tiles with ragged tails, radial flows through the mirrored axis, the
 finish / checkpoint paths, diagnostics, the error paths and the paper's own
@@ -7,7 +7,7 @@ L2 <= 1e-10 with FP64 populations, <= 1e-4 with FP32 populations."""
 import numpy as np
 import pytest
 
-from _pairs import FIELDS, FLUID, compare, make_pair
+from _pairs import FIELDS, FLUID, WARM, compare, make_pair
 from paper_2309_04872_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -16,26 +16,32 @@ TOL = {"fp64": 1e-10, "fp32": 1e-4, "fp16dev": 1e-2}
 Q_ALL = list(FLUID) + list(FIELDS) + ["ez_yee", "ex_yee", "by_yee"]
 
 
+def _q(closure):
+    return Q_ALL + (list(WARM) if closure == "warmc" else [])
+
+
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
-def test_axi_parity_driven(storage):
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_axi_parity_driven(closure, storage):
     """Driver on the axis, warm plasma with seeded noise; 100 x 21 nodes
-    (FP64 tiles 64 x 4, FP32 64 x 16: ragged in both directions)."""
+    (tiles 64 x 4, 64 x 16, 32 x 8: ragged in both directions)."""
     nz, nr = 100, 21
     d = 2 * np.pi / 32
     n = workloads.density_noise((nr, nz), 1e-3, 21)
-    print("axi driven", storage, nz, nr, flush=True)
-    s, o = make_pair(2, nz, nr, delta=d, closure="lec", storage=storage, mu=0.04, n=n, geom="axi",
+    print("axi driven", closure, storage, nz, nr, flush=True)
+    s, o = make_pair(2, nz, nr, delta=d, closure=closure, storage=storage, mu=0.04, n=n, geom="axi",
                      driver=dict(alpha=0.8, sigma_z=1.0, sigma_x=0.5, z0=4.0))
     s.step(60)
     o.step(60)
-    compare(s, o, Q_ALL, TOL[storage])
+    compare(s, o, _q(closure), TOL[storage])
 
 
-def test_axi_parity_fp16dev():
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_axi_parity_fp16dev(closure):
     nz, nr = 100, 21
     d = 2 * np.pi / 32
-    print("axi driven fp16dev", flush=True)
-    s, o = make_pair(2, nz, nr, delta=d, closure="lec", storage="fp16dev", mu=0.04, geom="axi",
+    print("axi driven fp16dev", closure, flush=True)
+    s, o = make_pair(2, nz, nr, delta=d, closure=closure, storage="fp16dev", mu=0.04, geom="axi",
                      driver=dict(alpha=0.8, sigma_z=1.0, sigma_x=0.5, z0=4.0))
     s.step(60)
     o.step(60)
@@ -43,7 +49,8 @@ def test_axi_parity_fp16dev():
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
-def test_axi_parity_radial_flow(storage):
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_axi_parity_radial_flow(closure, storage):
     """Periodic in z, no driver, an initial radial velocity that is nonzero
     next to the axis: every step streams the odd radial momentum through
     the mirrored ghost row and drives the -u_r A / r sources."""
@@ -53,18 +60,19 @@ def test_axi_parity_radial_flow(storage):
     ux = 0.05 * rr * np.exp(-rr ** 2 / 2.0) * (1 + 0.3 * np.cos(2 * np.pi * zz / (nz * d)))
     uz = 0.03 * np.sin(2 * np.pi * zz / (nz * d)) * np.exp(-rr ** 2 / 4.0)
     n = 1 + 0.02 * np.exp(-rr ** 2) + workloads.density_noise((nr, nz), 1e-4, 3) - 1
-    print("axi radial flow", storage, flush=True)
-    s, o = make_pair(2, nz, nr, delta=d, closure="lec", storage=storage, mu=0.02, n=n, uz=uz, ux=ux,
+    print("axi radial flow", closure, storage, flush=True)
+    s, o = make_pair(2, nz, nr, delta=d, closure=closure, storage=storage, mu=0.02, n=n, uz=uz, ux=ux,
                      bc_z="periodic", geom="axi")
     s.step(150)
     o.step(150)
-    compare(s, o, Q_ALL, TOL[storage])
+    compare(s, o, _q(closure), TOL[storage])
 
 
-def test_axi_rest_state_exact():
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_axi_rest_state_exact(closure):
     from paper_2309_04872_amd.sim import Sim
 
-    s = Sim(2, 70, 20, closure="lec", geom="axi", bc_z="periodic")
+    s = Sim(2, 70, 20, closure=closure, geom="axi", bc_z="periodic")
     s.init_plasma(0.04)
     s.step(50)
     assert np.abs(s.read("n") - 1).max() <= 1e-14
@@ -74,14 +82,15 @@ def test_axi_rest_state_exact():
         assert np.abs(s.field(q)).max() <= 1e-14, q
 
 
-def test_axi_split_steps_and_checkpoint_bitwise():
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_axi_split_steps_and_checkpoint_bitwise(closure):
     from paper_2309_04872_amd.sim import Sim
 
     nz, nr = 80, 24
     d = 2 * np.pi / 32
 
     def fresh():
-        s = Sim(2, nz, nr, delta=d, closure="lec", geom="axi")
+        s = Sim(2, nz, nr, delta=d, closure=closure, geom="axi")
         s.init_plasma(0.02, n=workloads.density_noise((nr, nz), 1e-3, 2))
         s.init_driver(0.4, 0.7, 0.5, z0=4.0)
         return s
@@ -101,12 +110,13 @@ def test_axi_split_steps_and_checkpoint_bitwise():
         assert np.array_equal(a.field(q), c.field(q)), q
 
 
-def test_axi_diagnostics_parity():
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_axi_diagnostics_parity(closure):
     """Volume-weighted sums (2 pi r), field energy and the cylindrical Gauss
     residual agree with the oracle's."""
     nz, nr = 128, 32
     d = 2 * np.pi / 32
-    s, o = make_pair(2, nz, nr, delta=d, closure="lec", mu=0.02, geom="axi",
+    s, o = make_pair(2, nz, nr, delta=d, closure=closure, mu=0.02, geom="axi",
                      n=workloads.density_noise((nr, nz), 1e-2, 4),
                      driver=dict(alpha=0.6, sigma_z=1.0, sigma_x=0.5, z0=4.0))
     s.step(40)
@@ -120,8 +130,6 @@ def test_axi_diagnostics_parity():
 def test_axi_error_paths():
     from paper_2309_04872_amd.sim import LbwError, Sim
 
-    with pytest.raises(LbwError, match="UNSUPPORTED"):
-        Sim(2, 64, 16, closure="warmc", geom="axi")
     with pytest.raises(LbwError, match="ARG"):
         Sim(2, 64, 16, closure="lec", geom="axi", bc_x="periodic")
     s = Sim(2, 64, 16, closure="lec", geom="axi")
@@ -143,15 +151,16 @@ def test_axi_error_paths():
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
-def test_axi_full_size_paper_grid(storage):
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_axi_full_size_paper_grid(closure, storage):
     """The paper's production grid (3000 x 600, delta = 0.01, mu = 0.04,
     Q~ = 0.5), 100 steps against the oracle on every node. Fewer steps leave
     u_z so small (rms 5e-9 after 8 steps) that its pressure-gradient source,
     a difference of neighbouring n0^{5/3} values equal to 1 within 1e-8,
     carries a relative rounding error above 1e-10 in any FP64 evaluation."""
-    w = workloads.workload("wake_axi_lec")
-    print("axi full size", storage, w["nz"], w["nx"], flush=True)
-    s, o = make_pair(2, w["nz"], w["nx"], delta=w["delta"], closure="lec", dvel=w["dvel"],
+    w = workloads.workload("wake_axi_" + closure)
+    print("axi full size", closure, storage, w["nz"], w["nx"], flush=True)
+    s, o = make_pair(2, w["nz"], w["nx"], delta=w["delta"], closure=closure, dvel=w["dvel"],
                      storage=storage, mu=w["mu"], geom="axi",
                      driver=dict(alpha=w["alpha"], sigma_z=w["sigma_z"], sigma_x=w["sigma_x"],
                                  z0=w["z0"]))
