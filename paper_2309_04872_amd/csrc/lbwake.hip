@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -47,12 +48,30 @@ namespace {
 #ifndef LBW_TX2_WF64
 #define LBW_TX2_WF64 8
 #endif
+#ifndef LBW_TZ2_S
+#define LBW_TZ2_S 64
+#endif
+#ifndef LBW_TX2_S
+#define LBW_TX2_S 8
+#endif
 #ifndef LBW_TZ1
 #define LBW_TZ1 256
 #endif
 template <int CL, class ST> struct Tile2 {  // local-equilibrium, FP32 / FP16 storage
     static constexpr int TZ = LBW_TZ2, TX = LBW_TX2, CPT = LBW_CPT2;
 };
+// Local equilibrium, FP32 / FP16 storage, second shape: 512-thread workgroups,
+// two per compute unit, so that one workgroup's loads overlap the other's
+// recovery, field update and collision. The 1024-thread 64 x 16 tile has the
+// smaller recovery ring (16 % of the tile instead of 29 %) and wins while the
+// populations sit largely in the 256 MB last-level cache; once the grid
+// streams from HBM the overlap wins (3000 x 600: 151 -> 143 us FP32,
+// 108 -> 97 us FP16; 4096 x 1024: 321 -> 298 us, 248 -> 228 us), and for FP16
+// it wins at 2048 x 512 too (52.1 -> 46.8 us; FP32 66.8 -> 69.5 us there).
+struct Tile2Stream {
+    static constexpr int TZ = LBW_TZ2_S, TX = LBW_TX2_S, CPT = 1;
+};
+constexpr size_t MALL_BYTES = size_t(256) << 20;
 template <> struct Tile2<LEC, double> {
     static constexpr int TZ = LBW_TZ2_F64, TX = LBW_TX2_F64, CPT = 1;
 };
@@ -207,14 +226,24 @@ void set_io(lbw_sim *s, StepArgs &a)
 }
 
 template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
+    template <class T> static void launch2d(const StepArgs &a, hipStream_t st)
+    {
+        // one-dimensional grid: the kernel maps blocks to tiles XCD by XCD
+        dim3 grid(((a.nz + T::TZ - 1) / T::TZ) * ((a.nx + T::TX - 1) / T::TX));
+        hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI>), grid, dim3(T::TZ * T::TX / T::CPT),
+                           0, st, a);
+    }
     static void step(const StepArgs &a, hipStream_t st)
     {
         if constexpr (DIM == 2) {
-            // one-dimensional grid: the kernel maps blocks to tiles XCD by XCD
-            using T = Tile2<CL, ST>;
-            dim3 grid(((a.nz + T::TZ - 1) / T::TZ) * ((a.nx + T::TX - 1) / T::TX));
-            hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI>), grid,
-                               dim3(T::TZ * T::TX / T::CPT), 0, st, a);
+            if constexpr (CL == LEC && !std::is_same<ST, double>::value) {
+                const size_t pop_bytes = (size_t)a.ncell * 2 * 27 * sizeof(ST);
+                if (std::is_same<ST, __half>::value || pop_bytes > MALL_BYTES) {
+                    launch2d<Tile2Stream>(a, st);
+                    return;
+                }
+            }
+            launch2d<Tile2<CL, ST>>(a, st);
         } else {
             dim3 grid((a.nz + TZ1 - 1) / TZ1);
             hipLaunchKernelGGL((k_step1d<CL, ST, TZ1>), grid, dim3(TZ1), 0, st, a);

@@ -125,6 +125,19 @@ def test_full_size_wake2d_lec(storage):
     compare(s, o, ["n", "uz", "ux", "ez", "ex", "by"], TOL[storage])
 
 
+def test_large_wake2d_lec_fp32_streaming_tile():
+    """4096 x 1024 FP32: populations beyond the last-level cache select the
+    512-thread 64 x 8 tile; 3 steps against the oracle."""
+    w = workloads.workload("wake2d_lec_fp32", nz=4096, nx=1024)
+    s, o = make_pair(2, w["nz"], w["nx"], delta=w["delta"], closure="lec", dvel=w["dvel"],
+                     storage="fp32", mu=w["mu"],
+                     driver=dict(alpha=w["alpha"], sigma_z=w["sigma_z"], sigma_x=w["sigma_x"],
+                                 z0=w["z0"]))
+    s.step(3)
+    o.step(3)
+    compare(s, o, ["n", "uz", "ux", "ez", "ex", "by"], TOL["fp32"])
+
+
 def test_full_size_wake2d_warmc_fp64():
     """4096 x 1024 warm-closure wake, 3 steps against the oracle."""
     w = workloads.workload("wake2d_warmc")
