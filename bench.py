@@ -58,7 +58,7 @@ TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake2d_warmc", "fp16dev"): 2119.3e6,
     ("wake_axi_lec", "fp64"): 1092.6e6,
     ("wake_axi_lec", "fp32"): 544.5e6,
-    ("wake_axi_warmc", "fp64"): 2935.1e6,
+    ("wake_axi_warmc", "fp64"): 3072.3e6,
     ("wake_axi_warmc", "fp32"): 1600.4e6,
 }
 

@@ -81,6 +81,12 @@ template <class ST> struct Tile2<WARMC, ST> {
 template <> struct Tile2<WARMC, double> {  // measured 3.6 % faster than 64 x 4 for FP64
     static constexpr int TZ = LBW_TZ2_WF64, TX = LBW_TX2_WF64, CPT = 1;
 };
+// Warm closure, FP64, axisymmetric geometry: 64 x 4 (the paper's 3000 x 600
+// grid: 573 us per step against 605 us with 32 x 8; both 256 threads and two
+// waves per SIMD, the slab 4096 x 1024 grid the other way round, 1355 / 1305).
+struct Tile2WarmAxi64 {
+    static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1;
+};
 constexpr int TZ1 = LBW_TZ1;  // 1D tile
 constexpr int MAX_SLICES = 4096;
 constexpr size_t ALIGN = 256;
@@ -242,6 +248,10 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
                     launch2d<Tile2Stream>(a, st);
                     return;
                 }
+            }
+            if constexpr (AXI && CL == WARMC && std::is_same<ST, double>::value) {
+                launch2d<Tile2WarmAxi64>(a, st);
+                return;
             }
             launch2d<Tile2<CL, ST>>(a, st);
         } else {
