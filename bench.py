@@ -53,7 +53,7 @@ def bytes_per_lu(dims, closure, storage):
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake2d_lec_fp32", "fp32"): 301.2e6,
     ("wake2d_lec_fp32", "fp64"): 605.7e6,
-    ("wake2d_warmc", "fp64"): 6871.6e6,
+    ("wake2d_warmc", "fp64"): 6685.6e6,
     ("wake2d_warmc", "fp32"): 3956.2e6,
     ("wake2d_warmc", "fp16dev"): 2119.4e6,
     ("wake_axi_lec", "fp64"): 1092.6e6,

@@ -91,7 +91,10 @@ __device__ __forceinline__ void collide_all(CT (*s)[Lattice<DIM>::Q], const doub
 // -u_r A / r plus, for the warm closure, the cylindrical parts of the tensor
 // divergences, and the E_z update takes the cylindrical curl
 // (1/r) d_r (r B_phi); E_r and B_phi vanish on the axis.
-template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false>
+// STRIP > 1: inside an XCD's band the tiles run z-major through strips of
+// STRIP tile-rows, so that the rows a tile shares with the tiles above and
+// below are still in that XCD's L2 when they are read again.
+template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false, int STRIP = 1>
 __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 {
     using L = Lattice<2>;
@@ -115,7 +118,17 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
     const size_t nc = (size_t)a.ncell;
     const int ntz = (nz + TZ - 1) / TZ;
     const int tile = xcd_band_tile(blockIdx.x, gridDim.x);
-    const int z0 = (tile % ntz) * TZ, x0 = (tile / ntz) * TX;
+    int z0, x0;
+    if constexpr (STRIP == 1) {
+        z0 = (tile % ntz) * TZ;
+        x0 = (tile / ntz) * TX;
+    } else {
+        const int ntx = (nx + TX - 1) / TX;
+        const int strip = tile / (STRIP * ntz), rr = tile % (STRIP * ntz);
+        const int rows = ntx - strip * STRIP < STRIP ? ntx - strip * STRIP : STRIP;  // last strip
+        z0 = (rr / rows) * TZ;
+        x0 = (strip * STRIP + rr % rows) * TX;
+    }
     const ST *src = (const ST *)a.src;
     ST *dst = (ST *)a.dst;
 

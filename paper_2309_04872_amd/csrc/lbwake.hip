@@ -58,7 +58,7 @@ namespace {
 #define LBW_TZ1 256
 #endif
 template <int CL, class ST> struct Tile2 {  // local-equilibrium, FP32 / FP16 storage
-    static constexpr int TZ = LBW_TZ2, TX = LBW_TX2, CPT = LBW_CPT2;
+    static constexpr int TZ = LBW_TZ2, TX = LBW_TX2, CPT = LBW_CPT2, STRIP = 1;
 };
 // Local equilibrium, FP32 / FP16 storage, second shape: 512-thread workgroups,
 // two per compute unit, so that one workgroup's loads overlap the other's
@@ -69,23 +69,26 @@ template <int CL, class ST> struct Tile2 {  // local-equilibrium, FP32 / FP16 st
 // 108 -> 97 us FP16; 4096 x 1024: 321 -> 298 us, 248 -> 228 us), and for FP16
 // it wins at 2048 x 512 too (52.1 -> 46.8 us; FP32 66.8 -> 69.5 us there).
 struct Tile2Stream {
-    static constexpr int TZ = LBW_TZ2_S, TX = LBW_TX2_S, CPT = 1;
+    static constexpr int TZ = LBW_TZ2_S, TX = LBW_TX2_S, CPT = 1, STRIP = 1;
 };
 constexpr size_t MALL_BYTES = size_t(256) << 20;
 template <> struct Tile2<LEC, double> {
-    static constexpr int TZ = LBW_TZ2_F64, TX = LBW_TX2_F64, CPT = 1;
+    static constexpr int TZ = LBW_TZ2_F64, TX = LBW_TX2_F64, CPT = 1, STRIP = 1;
 };
 template <class ST> struct Tile2<WARMC, ST> {
-    static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1;
+    static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1, STRIP = 1;
 };
-template <> struct Tile2<WARMC, double> {  // measured 3.6 % faster than 64 x 4 for FP64
-    static constexpr int TZ = LBW_TZ2_WF64, TX = LBW_TX2_WF64, CPT = 1;
+// measured 3.6 % faster than 64 x 4 for FP64; strips of 4 tile-rows: 4096 x 1024
+// 1310 -> 1246 us (strips of 1, 2, 4 measured for every 2D case: elsewhere within
+// +-2 % or slower)
+template <> struct Tile2<WARMC, double> {
+    static constexpr int TZ = LBW_TZ2_WF64, TX = LBW_TX2_WF64, CPT = 1, STRIP = 4;
 };
 // Warm closure, FP64, axisymmetric geometry: 64 x 4 (the paper's 3000 x 600
 // grid: 573 us per step against 605 us with 32 x 8; both 256 threads and two
 // waves per SIMD, the slab 4096 x 1024 grid the other way round, 1355 / 1305).
 struct Tile2WarmAxi64 {
-    static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1;
+    static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1, STRIP = 1;
 };
 constexpr int TZ1 = LBW_TZ1;  // 1D tile
 constexpr int MAX_SLICES = 4096;
@@ -236,8 +239,8 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
     {
         // one-dimensional grid: the kernel maps blocks to tiles XCD by XCD
         dim3 grid(((a.nz + T::TZ - 1) / T::TZ) * ((a.nx + T::TX - 1) / T::TX));
-        hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI>), grid, dim3(T::TZ * T::TX / T::CPT),
-                           0, st, a);
+        hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP>), grid,
+                           dim3(T::TZ * T::TX / T::CPT), 0, st, a);
     }
     static void step(const StepArgs &a, hipStream_t st)
     {
