@@ -37,6 +37,18 @@ def test_parity_1d_driven(closure, storage):
     compare(s, o, _quantities(closure, 1), TOL[storage])
 
 
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_parity_1d_long_grid(closure):
+    """9000 nodes: the persistent 1D kernel runs 1024-node tiles (512 below
+    8192 nodes); ragged last tile."""
+    nz = 9000
+    n = workloads.density_noise((1, nz), 1e-3, 17)[0]
+    s, o = make_pair(1, nz, closure=closure, mu=0.02, n=n, driver=dict(alpha=0.3, sigma_z=0.5, z0=3.0))
+    s.step(300)
+    o.step(300)
+    compare(s, o, _quantities(closure, 1), TOL["fp64"])
+
+
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 @pytest.mark.parametrize("closure", ["lec", "warmc"])
 def test_parity_2d_driven(closure, storage):
