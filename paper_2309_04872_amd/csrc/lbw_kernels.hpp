@@ -33,7 +33,7 @@ struct StepArgs {
     double delta, dt, inv2d, omega, lam, mu, a_lec, two_over_d;
     int dcode;                   // 1, 3 or 0 (general D)
     int do_pull, do_maxwell, lag_init;
-    int axi;                     // 2D local equilibrium: axisymmetric (z, r) geometry
+    int axi;                     // 2D: axisymmetric (z, r) geometry
     long step;
     Driver drv;
 };
