@@ -575,20 +575,147 @@ __global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
     step1d_tile<CL, ST, TZ>(a, blockIdx.x, s_g);
 }
 
+// Two local-equilibrium 1D steps in one pass over a tile (temporal
+// blocking). Slot r of the TZ threads holds node fix(z0 - 3 + r) under the
+// boundary rule; step t runs on slots [1, TZ - 1) and hands its
+// post-collision +z / -z populations to step t + 1 through LDS, rounded to
+// the storage type as a store and reload would round them; step t + 1 runs on
+// slots [2, TZ - 2) (recovery) and [3, TZ - 3) (collision), i.e. it writes
+// nodes [z0, z0 + TZ - 6). The per-node arithmetic is that of step1d_tile,
+// so a pair equals two single steps bit for bit. Input: the mid-step state
+// of step t - 1 (pull); E_z read from ez_in, written to ez_out.
+template <int TZ> constexpr int pair_width() { return TZ - 6; }
+
+template <class ST, int TZ>
+__device__ __forceinline__ void step1d_pair(const StepArgs &a, int tile, double (*s_g)[TZ + 2],
+                                            typename Store<ST>::ct (*xc)[2][TZ])
+{
+    using L = Lattice<1>;
+    using CT = typename Store<ST>::ct;
+    constexpr int Q = L::Q;
+    constexpr int K = NScal<1, LEC>::K;
+    const int tid = threadIdx.x;
+    const int nz = a.nz, bcz = a.bcz;
+    const size_t nc = (size_t)a.ncell;
+    const int off = tile * pair_width<TZ>() - 3;  // node of slot 0 before the boundary rule
+    const ST *src = (const ST *)a.src;
+    ST *dst = (ST *)a.dst;
+    const double dt = a.dt;
+    double aref[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) aref[k] = a.aref[k];
+    // LDS slot holding the neighbour d of slot r's node
+    auto nb = [&](int r, int d) {
+        return bcz == BC_PERIODIC ? r + d : map_node(fix_node(off + r, nz, bcz) + d, nz, bcz) - off;
+    };
+    auto moments = [&](CT (*s)[Q], double *A) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            CT acc = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc += s[k][q];
+            A[k] = aref[k] + (double)acc;
+        }
+    };
+    auto recover = [&](const double *A, int r, double &uz) {
+        LecRec l;
+        if (!lec_recover(A[0], A[1], 0.0, a.a_lec, a.dcode, a.two_over_d, l)) {
+            if (a.fallbacks) atomicAdd(a.fallbacks, 1u);
+        }
+        uz = l.uz;
+        s_g[0][r] = l.phi;
+    };
+    auto force_collide = [&](CT (*s)[Q], const double *A, double uz, double Ez, int r) {
+        double F[K];
+        F[0] = 0.0;
+        F[1] = -a.mu * ((s_g[0][nb(r, 1)] - s_g[0][nb(r, -1)]) * a.inv2d) - A[0] * Ez;
+        collide_all<1, K, CT>(s, A, aref, F, uz, 0.0, a.lam, a.omega, dt);
+    };
+    auto rnd = [](CT v) { return (CT)Store<ST>::rnd(v); };
+
+    // ---- step t on every slot
+    const int z = fix_node(off + tid, nz, bcz);
+    CT s[K][Q];
+    double A[K], uz;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int c = fix_node(z - L::ez(q), nz, bcz);
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
+    }
+    double Ez = a.ez_in[z];
+    moments(s, A);
+    recover(A, tid, uz);
+    __syncthreads();
+    CT rest[K];
+    if (tid >= 1 && tid < TZ - 1) {
+        const double jb = driver_density<1>(a.drv, z * a.delta, 0.0, (a.step - 0.5) * dt);
+        Ez = Ez + dt * (A[0] * uz + jb);
+        force_collide(s, A, uz, Ez, tid);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            rest[k] = rnd(s[k][0]);
+            xc[k][0][tid] = rnd(s[k][1]);
+            xc[k][1][tid] = rnd(s[k][2]);
+        }
+    }
+    __syncthreads();  // movers in LDS; every step-t value of phi has been read
+    // ---- step t + 1: pull from LDS, recovery
+    if (tid >= 2 && tid < TZ - 2) {
+        const int rm = nb(tid, -1), rp = nb(tid, 1);  // sources of the +z and -z movers
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            s[k][0] = rest[k];
+            s[k][1] = xc[k][0][rm];
+            s[k][2] = xc[k][1][rp];
+        }
+        moments(s, A);
+        recover(A, tid, uz);
+    }
+    __syncthreads();
+    const int zo = off + tid;
+    if (tid >= 3 && tid < TZ - 3 && zo < nz) {
+        const double jb = driver_density<1>(a.drv, zo * a.delta, 0.0, (a.step + 0.5) * dt);
+        Ez = Ez + dt * (A[0] * uz + jb);
+        force_collide(s, A, uz, Ez, tid);
+        a.ez_out[zo] = Ez;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) Store<ST>::st(dst + (size_t)(k * Q + q) * nc, zo, s[k][q]);
+    }
+    __syncthreads();  // the LDS slots are reused by the next tile or pass
+}
+
+// Passes of the persistent 1D kernel for nsteps steps: the first step from
+// the canonical state as a single step, then (local equilibrium) pairs of
+// steps, and a single step when one is left. Each pass swaps the population
+// and E_z buffers once.
+__host__ __device__ inline int persist_passes(int closure, int nsteps)
+{
+    if (closure != LEC || nsteps <= 1) return nsteps;
+    const int rest = nsteps - 1;
+    return 1 + rest / 2 + (rest & 1);
+}
+
 // All steps of one lbw_step call in one cooperative launch (1D grids small
 // enough for every workgroup to be resident): the workgroups sweep their
-// tiles, then wait for the whole grid before the next step reads its
-// neighbours. Buffers alternate as between separate launches; a.src / a.dst
-// and the E_z arrays are those of the first step.
+// tiles, then wait for the whole grid before the next pass reads its
+// neighbours. Buffers alternate per pass as between separate launches;
+// a.src / a.dst and the E_z arrays are those of the first pass.
 template <int CL, class ST, int TZ>
 __global__ __launch_bounds__(TZ) void k_step1d_persist(StepArgs a, int nsteps)
 {
+    using CT = typename Store<ST>::ct;
     constexpr int NG = CL == LEC ? 1 : 3;
     __shared__ double s_g[NG][TZ + 2];
+    __shared__ CT s_xc[CL == LEC ? 2 : 1][2][CL == LEC ? TZ : 1];
     const int ntiles = (a.nz + TZ - 1) / TZ;
-    for (int t = 0; t < nsteps; ++t) {
+    const int ntiles2 = (a.nz + pair_width<TZ>() - 1) / pair_width<TZ>();
+    int t = 0, pass = 0;
+    while (t < nsteps) {
         StepArgs b = a;
-        if (t & 1) {
+        if (pass & 1) {
             b.src = a.dst;
             b.dst = (void *)a.src;
             b.ez_in = a.ez_out;
@@ -600,7 +727,15 @@ __global__ __launch_bounds__(TZ) void k_step1d_persist(StepArgs a, int nsteps)
             b.lag_init = 0;
         }
         b.step = a.step + t;
-        for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) step1d_tile<CL, ST, TZ>(b, tile, s_g);
+        if (CL == LEC && t > 0 && nsteps - t >= 2) {
+            if constexpr (CL == LEC)
+                for (int tile = blockIdx.x; tile < ntiles2; tile += gridDim.x) step1d_pair<ST, TZ>(b, tile, s_g, s_xc);
+            t += 2;
+        } else {
+            for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) step1d_tile<CL, ST, TZ>(b, tile, s_g);
+            t += 1;
+        }
+        ++pass;
         __ockl_grid_sync();
     }
 }

@@ -276,7 +276,9 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step1d_persist<CL, ST, TZ>, TZ, 0) != hipSuccess)
             return 0;
-        const int ntiles = (nz + TZ - 1) / TZ;
+        // local equilibrium: pairs of steps run on tiles of TZ - 6 nodes
+        const int t1 = (nz + TZ - 1) / TZ, t2 = (nz + pair_width<TZ>() - 1) / pair_width<TZ>();
+        const int ntiles = CL == LEC && t2 > t1 ? t2 : t1;
         const int maxg = per * cus;
         return ntiles < maxg ? ntiles : maxg;
     }
@@ -697,8 +699,9 @@ lbw_status lbw_step(lbw_sim *s, int nsteps)
         a.do_maxwell = s->canonical ? 0 : 1;
         a.lag_init = s->lag_valid ? 0 : 1;
         HIPCHK(s, ops.step_persist(a, nsteps, s->persist, s->stream));
-        s->pcur ^= nsteps & 1;
-        s->fcur ^= nsteps & 1;
+        const int passes = persist_passes(s->g.closure, nsteps);  // buffer swaps
+        s->pcur ^= passes & 1;
+        s->fcur ^= passes & 1;
         s->canonical = false;
         s->lag_valid = true;
         s->step += nsteps;
