@@ -49,6 +49,11 @@ __device__ __forceinline__ int pre1(int y, int d, int n, int bc, bool stag, int 
         out[0] = c < 0 ? c + n : c;
         return 1;
     }
+    // away from the ends no clamped read lands on y (|d| <= 1): y - d only
+    if (y >= 1 && y <= n - 3) {
+        out[0] = y - d;
+        return 1;
+    }
     const int cand[4] = {y - d, 0, n - 2, n - 1};
     int cnt = 0;
 #pragma unroll
