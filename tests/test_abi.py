@@ -60,6 +60,20 @@ def test_workspace_bytes(lib):
     assert lib.lbw_workspace_bytes(ctypes.byref(_grid(closure=5))) == 0
 
 
+def test_grid_size_limit(lib):
+    """Node offsets inside a population plane and every plane offset times
+    72 planes stay below 2^31: grids beyond 2e9 / 72 nodes are rejected, the
+    largest accepted one needs its full workspace (no overflow in the size)."""
+    limit = int(2.0e9 / 72)
+    nx = 1024
+    nz_ok = limit // nx
+    g_ok = _grid(nz=nz_ok, nx=nx, closure=1)
+    n_ok = lib.lbw_workspace_bytes(ctypes.byref(g_ok))
+    assert n_ok >= 2 * 72 * nz_ok * nx * 8
+    assert lib.lbw_workspace_bytes(ctypes.byref(_grid(nz=nz_ok + 2, nx=nx))) == 0
+    assert lib.lbw_workspace_bytes(ctypes.byref(_grid(nz=4, nx=4))) > 0  # smallest 2D grid
+
+
 def test_geometry_validation(lib):
     """The axisymmetric geometry is 2D with an open outer radius, for both
     closures; it needs the workspace of the slab grid."""
