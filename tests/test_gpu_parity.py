@@ -150,6 +150,55 @@ def test_large_wake2d_lec_fp32_streaming_tile():
     compare(s, o, ["n", "uz", "ux", "ez", "ex", "by"], TOL["fp32"])
 
 
+def _corner_bump(nz, nx, dz, dx, amp=0.05, width=3.0):
+    """Density 1 plus a Gaussian bump (dz, dx) nodes in from the top corner."""
+    z = np.arange(nz) - (nz - 1 - dz)
+    x = np.arange(nx) - (nx - 1 - dx)
+    return 1.0 + amp * np.exp(-(x[:, None] ** 2 + z[None, :] ** 2) / (2 * width ** 2))
+
+
+def test_maximum_size_indexing():
+    """The largest accepted grid (2e9 / 72 nodes) with the warm closure and
+    FP16 storage, whose 72 population planes reach element offsets near
+    2^31: a density bump next to the far corner evolves exactly as the same
+    bump next to the corner of a 512 x 256 grid that runs the same kernel,
+    bit for bit in the corner region (20 steps: nothing from the far
+    boundaries of the small grid, 196 and 372 nodes away, reaches it). Same
+    in 1D at the largest length against 16384 nodes (both above 8192, so the
+    same persistent-kernel tile)."""
+    from paper_2309_04872_amd.sim import Sim
+
+    limit = int(2.0e9 / 72)
+    nxl = 1024
+    nzl = limit // nxl
+    big = (nzl, nxl)
+    small = (512, 256)
+    out = []
+    for nz, nx in (big, small):
+        print("max-size indexing 2D", nz, nx, flush=True)
+        s = Sim(2, nz, nx, closure="warmc", storage="fp16dev", delta=2 * np.pi / 64)
+        s.init_plasma(0.02, n=_corner_bump(nz, nx, 60, 20))
+        s.step(20)
+        out.append({q: s.read(q)[-60:, -140:] for q in ("n", "uz", "ux", "thzz")} |
+                   {"ez": s.field("ez")[-60:, -140:]})
+        del s
+    assert np.abs(out[1]["ux"]).max() > 1e-4 and np.abs(out[1]["ez"]).max() > 1e-6  # the bump has moved
+    for q in out[0]:
+        assert np.array_equal(out[0][q], out[1][q]), q
+    out = []
+    for nz in (limit, 16384):
+        print("max-size indexing 1D", nz, flush=True)
+        s = Sim(1, nz, closure="lec", delta=2 * np.pi / 128)
+        z = np.arange(nz) - (nz - 1 - 100)
+        s.init_plasma(1e-3, n=1.0 + 0.05 * np.exp(-z ** 2 / 18.0))
+        s.step(40)
+        out.append({"n": s.read("n")[-300:], "uz": s.read("uz")[-300:], "ez": s.field("ez")[-300:]})
+        del s
+    assert np.abs(out[1]["uz"]).max() > 1e-4
+    for q in out[0]:
+        assert np.array_equal(out[0][q], out[1][q]), q
+
+
 def test_full_size_wake2d_warmc_fp64():
     """4096 x 1024 warm-closure wake, 3 steps against the oracle."""
     w = workloads.workload("wake2d_warmc")
