@@ -17,10 +17,16 @@ Parity status (the ``-m "not gpu"`` tests under ``tests/test_oracle_*.py``):
   finite-k Langmuir dispersion along z and x, the transverse electromagnetic
   wave along z and x, the cold linear wake and the warm wake wavelength, the
   relativistic and warm nonlinear uniform oscillations (exact periods, energy
-  and trace-condition invariants), the initial fields, and mirror symmetry;
-- parity unpinned: the 2D-only nonlinear cross terms of the warm closure
-  (products of two perturbations, e.g. theta^{xz} d_x(lambda u_z)); they enter
-  only the nonlinear 2D regime and are covered by mirror symmetry alone.
+  and trace-condition invariants), the initial fields, mirror symmetry, and
+  rotation covariance in the (x, z) plane (a large-amplitude wave travelling
+  obliquely against the same wave along z, converging with resolution), which
+  pins the 2D-only nonlinear cross terms of the warm closure (products of two
+  perturbations, e.g. theta^{xz} d_x(lambda u_z));
+- axisymmetric geometry (``tests/test_oracle_axi.py``): pinned by the
+  cylindrical Gauss law, the local cold wake, an exact nonlinear breathing
+  column and the column's Langmuir modes; parity unpinned: the nonlinear
+  source -u_r lambda theta^{rz} / r of the warm closure, which no linear or
+  exact solution used there reaches.
 """
 from __future__ import annotations
 

@@ -525,6 +525,96 @@ def test_mirror_symmetry_2d(oracle_mod, closure):
 
 
 # ---------------------------------------------------------------------------
+# Rotation covariance in the (x, z) plane. Both closures are written with
+# vectors and tensors (Secs. 3 and 4, App. A with the 1/r terms dropped), so a
+# plane Langmuir wave travelling along s = (3 x + 4 z)/5 must be, in the frame
+# (s, t) with t = (4 x - 3 z)/5, the same wave as one travelling along z, up to
+# the lattice's anisotropy, which vanishes as delta -> 0. On an N x N periodic
+# grid with N = 5 M the oblique wave is a function of p = (3 i_x + 4 i_z) mod N
+# alone (the shift (4, -3) keeps p and generates every such translation), and
+# the nodes with p = 5 m carry the phase of node m of the wave along z on M
+# nodes. The oblique wave drives every cross term of the warm closure that the
+# wave along z leaves at zero (u_x u_z, theta^{xz}, theta^{0x}); at u = 0.2
+# those are a few per cent of the motion, so a dropped or wrongly signed one
+# leaves a difference that does not shrink with delta.
+
+def _oblique_vs_axis(oracle_mod, closure, npw, u0=0.2, mu=0.1, k=1.5, periods=0.5):
+    """Maximum differences, oblique wave minus wave along z, at the nodes
+    with p = 5 m, relative to each quantity's amplitude: density, lambda,
+    velocity along s and across it, E along s, B_y, and theta^{ss},
+    theta^{tt}, theta^{st} (theta^{zz}, theta^{xx}, 0 for the wave along z)."""
+    M, N = npw, 5 * npw
+    d = 2 * np.pi / (npw * k)
+    steps = int(round(periods * 2 * np.pi / (0.1 * d)))
+    warm = closure == 1
+    qs = ["n", "uz", "ux", "ez", "ex", "by"] + (["lambda", "thzz", "thxx", "thxz"] if warm else [])
+    a = oracle_mod.Oracle(2, M, 4, delta=d, closure=closure, mu=mu,
+                          bc_z=oracle_mod.PERIODIC, bc_x=oracle_mod.PERIODIC)
+    a.init(uz=np.broadcast_to(u0 * np.sin(2 * np.pi * np.arange(M) / M), (4, M)), ux=0.0,
+           fields_from_driver=False)
+    a.step(steps)
+    A = {q: a.get(q)[0] for q in qs}
+    b = oracle_mod.Oracle(2, N, N, delta=d, closure=closure, mu=mu,
+                          bc_z=oracle_mod.PERIODIC, bc_x=oracle_mod.PERIODIC)
+    ix, iz = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")  # [nx][nz]
+    p = (3 * ix + 4 * iz) % N
+    us = u0 * np.sin(2 * np.pi * p / N)
+    b.init(uz=0.8 * us, ux=0.6 * us, fields_from_driver=False)
+    b.step(steps)
+    sel = p % 5 == 0
+    m = p[sel] // 5
+    B = {q: b.get(q)[sel] for q in qs}
+    cx, cz = 0.6, 0.8  # s = (cx, cz) in (x, z); t = (cz, -cx)
+    obl = {"n": B["n"], "us": cx * B["ux"] + cz * B["uz"], "ut": cz * B["ux"] - cx * B["uz"],
+           "es": cx * B["ex"] + cz * B["ez"], "by": B["by"]}
+    ref = {"n": A["n"][m], "us": A["uz"][m], "ut": A["ux"][m], "es": A["ez"][m], "by": A["by"][m]}
+    amp = {"n": np.ptp(A["n"]) / 2, "us": np.abs(A["uz"]).max(), "ut": np.abs(A["uz"]).max(),
+           "es": np.abs(A["ez"]).max(), "by": np.abs(A["ez"]).max()}
+    if warm:
+        obl.update(lam=B["lambda"],
+                   thss=cx * cx * B["thxx"] + 2 * cx * cz * B["thxz"] + cz * cz * B["thzz"],
+                   thtt=cz * cz * B["thxx"] - 2 * cx * cz * B["thxz"] + cx * cx * B["thzz"],
+                   thst=cx * cz * (B["thxx"] - B["thzz"]) + (cz * cz - cx * cx) * B["thxz"])
+        ref.update(lam=A["lambda"][m], thss=A["thzz"][m], thtt=A["thxx"][m], thst=A["thxz"][m])
+        amp.update(lam=np.ptp(A["lambda"]) / 2, thss=np.ptp(A["thzz"]) / 2, thtt=np.ptp(A["thxx"]) / 2,
+                   thst=np.ptp(A["thzz"]) / 2)
+    assert np.ptp(b.get("n")[p == 5]) == 0.0  # a function of p alone
+    return {q: np.abs(obl[q] - ref[q]).max() / amp[q] for q in obl}
+
+
+# twice the differences measured at 48 nodes per wavelength
+BOUND_OBLIQUE = {
+    0: dict(n=3.1e-2, us=3.3e-3, ut=1.0e-3, es=4.5e-2, by=1.1e-2),
+    1: dict(n=3.5e-2, us=5.8e-3, ut=6.5e-4, es=2.0e-2, by=5.6e-3, lam=2.5e-2, thss=4.4e-2, thtt=3.5e-2,
+            thst=1.8e-3),
+}
+
+
+@pytest.mark.parametrize("closure", [0, 1])
+def test_rotation_covariance_oblique_wave(oracle_mod, closure):
+    """Half a plasma period of a u = 0.2 wave (k = 1.5, mu = 0.1) at 24 and
+    48 nodes per wavelength: every difference shrinks at least 2.2x when the
+    resolution doubles (measured 2.4x ... 5.7x) and stays below twice its
+    measured value at 48 nodes. Each of these mistakes planted in the warm
+    closure fails both checks (largest factor over the bound at 48 nodes):
+    -2 theta^{xz} d_x(lambda u_z) dropped from F(lambda theta^{zz}) (15x, on
+    theta^{st}), -2 theta^{xz} d_z(lambda u_x) dropped from F(lambda
+    theta^{xx}) (15x); the sign of -theta^{xz} d_x(lambda u_x) (6.4x) or of
+    -theta^{xz} d_z(lambda u_z) (12x) in F(lambda theta^{xz}) flipped;
+    -theta^{0z} d_t(lambda u_x) dropped from F(lambda theta^{xz}) (2.3x),
+    -2 theta^{0x} d_t(lambda u_x) from F(lambda theta^{xx}) (5.4x); u_z
+    theta^{xz} dropped from theta^{0x} (6.8x, on u_t); -d_x theta^{0x} dropped
+    from F(n lambda) (12x, on lambda)."""
+    d24 = _oblique_vs_axis(oracle_mod, closure, 24)
+    d48 = _oblique_vs_axis(oracle_mod, closure, 48)
+    print({q: (float(f"{d24[q]:.3g}"), float(f"{d48[q]:.3g}")) for q in d24})
+    bound = BOUND_OBLIQUE[closure]
+    for q in d48:
+        assert d48[q] <= d24[q] / 2.2, q
+        assert d48[q] <= bound[q], q
+
+
+# ---------------------------------------------------------------------------
 # Large-amplitude uniform oscillations (nonlinear terms). For a uniform state
 # every scalar obeys dA/dt = F exactly as above, so the continuum dynamics is
 # an ODE with closed-form integrals:
