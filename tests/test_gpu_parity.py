@@ -77,6 +77,24 @@ def test_parity_2d_periodic_waves(closure):
     compare(s, o, _quantities(closure, 2), 1e-10)
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_parity_oblique_large_wave(closure, storage):
+    """The oracle's rotation-covariance case: a u = 0.2, mu = 0.1 Langmuir
+    wave along (3, 4)/5 on a periodic 120 x 120 grid, half a plasma period
+    (every cross term of the warm closure at a few per cent of the motion)."""
+    N, k = 120, 1.5
+    d = 2 * np.pi / (24 * k)
+    ix, iz = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    us = 0.2 * np.sin(2 * np.pi * ((3 * ix + 4 * iz) % N) / N)
+    print("oblique wave", closure, storage, flush=True)
+    s, o = make_pair(2, N, N, delta=d, closure=closure, storage=storage, mu=0.1, uz=0.8 * us, ux=0.6 * us,
+                     bc_z="periodic", bc_x="periodic")
+    s.step(180)
+    o.step(180)
+    compare(s, o, _quantities(closure, 2), TOL[storage])
+
+
 @pytest.mark.parametrize("closure", ["lec", "warmc"])
 def test_parity_1d_periodic_relativistic(closure):
     nz = 300
