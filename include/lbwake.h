@@ -132,8 +132,9 @@ typedef struct {
 typedef struct lbw_sim lbw_sim;
 
 /* Bytes of device workspace a simulation of this grid needs (0 if the
- * descriptor is invalid or unsupported). The workspace must be 256-byte
- * aligned. */
+ * descriptor is invalid or unsupported, which includes grids of more than
+ * 2e9 / 72 nodes: population offsets are 32-bit). The workspace must be
+ * 256-byte aligned. */
 size_t lbw_workspace_bytes(const lbw_grid_desc *grid);
 
 /* Validate the grid (tau~ > 1/2, Courant dt <= delta / sqrt(dims)) and bind
