@@ -575,21 +575,23 @@ __global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
     step1d_tile<CL, ST, TZ>(a, blockIdx.x, s_g);
 }
 
-// Two local-equilibrium 1D steps in one pass over a tile (temporal
-// blocking). Slot r of the TZ threads holds node fix(z0 - 3 + r) under the
-// boundary rule; step t runs on slots [1, TZ - 1) and hands its
-// post-collision +z / -z populations to step t + 1 through LDS, rounded to
-// the storage type as a store and reload would round them; step t + 1 runs on
-// slots [2, TZ - 2) (recovery) and [3, TZ - 3) (collision), i.e. it writes
-// nodes [z0, z0 + TZ - 6). The per-node arithmetic is that of step1d_tile,
-// so a pair equals two single steps bit for bit. Input: the mid-step state
-// of step t - 1 (pull); E_z read from ez_in, written to ez_out.
-template <int TZ> constexpr int pair_width() { return TZ - 6; }
+// S local-equilibrium 1D steps in one pass over a tile (temporal blocking).
+// Slot r of the TZ threads holds node fix(z0 - (2S - 1) + r) under the
+// boundary rule. Step 0 of the pass recovers every slot and collides on
+// slots [1, TZ - 1); each later step m pulls its +z / -z populations from the
+// previous step's through LDS (rounded to the storage type as a store and
+// reload would round them), recovers on slots [2m, TZ - 2m) and collides on
+// [2m + 1, TZ - 2m - 1), so step S - 1 writes nodes [z0, z0 + TZ - 4S + 2).
+// The per-node arithmetic is that of step1d_tile, so a pass equals S single
+// steps bit for bit. Input: the mid-step state of the step before the pass
+// (pull); E_z read from ez_in, written to ez_out.
+template <int TZ, int S> constexpr int multi_width() { return TZ - 4 * S + 2; }
 
-template <class ST, int TZ>
-__device__ __forceinline__ void step1d_pair(const StepArgs &a, int tile, double (*s_g)[TZ + 2],
-                                            typename Store<ST>::ct (*xc)[2][TZ])
+template <class ST, int TZ, int S>
+__device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double (*s_g)[TZ + 2],
+                                             typename Store<ST>::ct (*xc)[2][TZ])
 {
+    static_assert(S >= 2 && multi_width<TZ, S>() > 0, "pass depth");
     using L = Lattice<1>;
     using CT = typename Store<ST>::ct;
     constexpr int Q = L::Q;
@@ -597,7 +599,7 @@ __device__ __forceinline__ void step1d_pair(const StepArgs &a, int tile, double 
     const int tid = threadIdx.x;
     const int nz = a.nz, bcz = a.bcz;
     const size_t nc = (size_t)a.ncell;
-    const int off = tile * pair_width<TZ>() - 3;  // node of slot 0 before the boundary rule
+    const int off = tile * multi_width<TZ, S>() - (2 * S - 1);  // node of slot 0 before the boundary rule
     const ST *src = (const ST *)a.src;
     ST *dst = (ST *)a.dst;
     const double dt = a.dt;
@@ -633,7 +635,7 @@ __device__ __forceinline__ void step1d_pair(const StepArgs &a, int tile, double 
     };
     auto rnd = [](CT v) { return (CT)Store<ST>::rnd(v); };
 
-    // ---- step t on every slot
+    // ---- step 0 of the pass on every slot
     const int z = fix_node(off + tid, nz, bcz);
     CT s[K][Q];
     double A[K], uz;
@@ -659,43 +661,65 @@ __device__ __forceinline__ void step1d_pair(const StepArgs &a, int tile, double 
             xc[k][1][tid] = rnd(s[k][2]);
         }
     }
-    __syncthreads();  // movers in LDS; every step-t value of phi has been read
-    // ---- step t + 1: pull from LDS, recovery
-    if (tid >= 2 && tid < TZ - 2) {
-        const int rm = nb(tid, -1), rp = nb(tid, 1);  // sources of the +z and -z movers
+    __syncthreads();  // movers in LDS; every value of phi has been read
+    // ---- steps 1 .. S - 1: pull from LDS, recovery, collision
+    for (int m = 1; m < S; ++m) {
+        if (tid >= 2 * m && tid < TZ - 2 * m) {
+            const int rm = nb(tid, -1), rp = nb(tid, 1);  // sources of the +z and -z movers
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            s[k][0] = rest[k];
-            s[k][1] = xc[k][0][rm];
-            s[k][2] = xc[k][1][rp];
+            for (int k = 0; k < K; ++k) {
+                s[k][0] = rest[k];
+                s[k][1] = xc[k][0][rm];
+                s[k][2] = xc[k][1][rp];
+            }
+            moments(s, A);
+            recover(A, tid, uz);
         }
-        moments(s, A);
-        recover(A, tid, uz);
-    }
-    __syncthreads();
-    const int zo = off + tid;
-    if (tid >= 3 && tid < TZ - 3 && zo < nz) {
-        const double jb = driver_density<1>(a.drv, zo * a.delta, 0.0, (a.step + 0.5) * dt);
-        Ez = Ez + dt * (A[0] * uz + jb);
-        force_collide(s, A, uz, Ez, tid);
-        a.ez_out[zo] = Ez;
+        __syncthreads();  // phi visible; every mover has been read
+        if (tid >= 2 * m + 1 && tid < TZ - 2 * m - 1) {
+            const int zm = fix_node(off + tid, nz, bcz);
+            const double jb = driver_density<1>(a.drv, zm * a.delta, 0.0, (a.step + m - 0.5) * dt);
+            Ez = Ez + dt * (A[0] * uz + jb);
+            force_collide(s, A, uz, Ez, tid);
+            if (m < S - 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+                for (int k = 0; k < K; ++k) {
+                    rest[k] = rnd(s[k][0]);
+                    xc[k][0][tid] = rnd(s[k][1]);
+                    xc[k][1][tid] = rnd(s[k][2]);
+                }
+            } else {
+                const int zo = off + tid;
+                if (zo < nz) {
+                    a.ez_out[zo] = Ez;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) Store<ST>::st(dst + (size_t)(k * Q + q) * nc, zo, s[k][q]);
+                    for (int k = 0; k < K; ++k)
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) Store<ST>::st(dst + (size_t)(k * Q + q) * nc, zo, s[k][q]);
+                }
+            }
+        }
+        __syncthreads();  // movers in LDS (or the tile done); every value of phi has been read
     }
-    __syncthreads();  // the LDS slots are reused by the next tile or pass
 }
 
 // Passes of the persistent 1D kernel for nsteps steps: the first step from
-// the canonical state as a single step, then (local equilibrium) pairs of
-// steps, and a single step when one is left. Each pass swaps the population
-// and E_z buffers once.
+// the canonical state as a single step, then (local equilibrium) passes of
+// PERSIST_DEPTH steps, pairs of steps for what is left, and a single step
+// when one is left. Each pass swaps the population and E_z buffers once.
+// Measured per step (4096 / 16384 nodes): 3.10 / 4.51 us with passes of 2
+// steps, 2.41 / 3.70 (4), 2.02 / 2.88 (8), 1.89 / 2.58 (16), 1.83 / 2.48
+// (24), 1.82 / 2.45 (32): past 24 the pass's own step latency dominates and
+// the redundant halo work (4 nodes per step) grows.
+#ifndef LBW_PERSIST_DEPTH
+#define LBW_PERSIST_DEPTH 24
+#endif
+constexpr int PERSIST_DEPTH = LBW_PERSIST_DEPTH;
 __host__ __device__ inline int persist_passes(int closure, int nsteps)
 {
     if (closure != LEC || nsteps <= 1) return nsteps;
-    const int rest = nsteps - 1;
-    return 1 + rest / 2 + (rest & 1);
+    const int rest = nsteps - 1, tail = rest % PERSIST_DEPTH;
+    return 1 + rest / PERSIST_DEPTH + tail / 2 + (tail & 1);
 }
 
 // All steps of one lbw_step call in one cooperative launch (1D grids small
@@ -711,7 +735,8 @@ __global__ __launch_bounds__(TZ) void k_step1d_persist(StepArgs a, int nsteps)
     __shared__ double s_g[NG][TZ + 2];
     __shared__ CT s_xc[CL == LEC ? 2 : 1][2][CL == LEC ? TZ : 1];
     const int ntiles = (a.nz + TZ - 1) / TZ;
-    const int ntiles2 = (a.nz + pair_width<TZ>() - 1) / pair_width<TZ>();
+    const int ntiles2 = (a.nz + multi_width<TZ, 2>() - 1) / multi_width<TZ, 2>();
+    const int ntilesd = (a.nz + multi_width<TZ, PERSIST_DEPTH>() - 1) / multi_width<TZ, PERSIST_DEPTH>();
     int t = 0, pass = 0;
     while (t < nsteps) {
         StepArgs b = a;
@@ -727,9 +752,14 @@ __global__ __launch_bounds__(TZ) void k_step1d_persist(StepArgs a, int nsteps)
             b.lag_init = 0;
         }
         b.step = a.step + t;
-        if (CL == LEC && t > 0 && nsteps - t >= 2) {
+        if (CL == LEC && t > 0 && nsteps - t >= PERSIST_DEPTH) {
             if constexpr (CL == LEC)
-                for (int tile = blockIdx.x; tile < ntiles2; tile += gridDim.x) step1d_pair<ST, TZ>(b, tile, s_g, s_xc);
+                for (int tile = blockIdx.x; tile < ntilesd; tile += gridDim.x)
+                    step1d_multi<ST, TZ, PERSIST_DEPTH>(b, tile, s_g, s_xc);
+            t += PERSIST_DEPTH;
+        } else if (CL == LEC && t > 0 && nsteps - t >= 2) {
+            if constexpr (CL == LEC)
+                for (int tile = blockIdx.x; tile < ntiles2; tile += gridDim.x) step1d_multi<ST, TZ, 2>(b, tile, s_g, s_xc);
             t += 2;
         } else {
             for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) step1d_tile<CL, ST, TZ>(b, tile, s_g);

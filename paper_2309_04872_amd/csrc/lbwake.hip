@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -276,9 +277,10 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step1d_persist<CL, ST, TZ>, TZ, 0) != hipSuccess)
             return 0;
-        // local equilibrium: pairs of steps run on tiles of TZ - 6 nodes
-        const int t1 = (nz + TZ - 1) / TZ, t2 = (nz + pair_width<TZ>() - 1) / pair_width<TZ>();
-        const int ntiles = CL == LEC && t2 > t1 ? t2 : t1;
+        // local equilibrium: passes of S steps run on tiles of TZ - 4S + 2 nodes
+        const int t1 = (nz + TZ - 1) / TZ, t2 = (nz + multi_width<TZ, 2>() - 1) / multi_width<TZ, 2>();
+        const int td = (nz + multi_width<TZ, PERSIST_DEPTH>() - 1) / multi_width<TZ, PERSIST_DEPTH>();
+        const int ntiles = CL == LEC ? std::max(t1, std::max(t2, td)) : t1;
         const int maxg = per * cus;
         return ntiles < maxg ? ntiles : maxg;
     }
