@@ -252,8 +252,9 @@ lbw_status lbw_adjoint_init_fields(lbw_sim *sim, const double *adj, double *grad
  * share the launch. lbw_batch_step runs all requested steps of every
  * instance inside one persistent kernel launch: one workgroup owns one
  * instance for the whole launch and advances it in passes separated by
- * workgroup barriers (two steps per pass after the first step, the state
- * read and written once per two steps), so no instance ever waits on another
+ * workgroup barriers (after the first step, passes of 16 steps and then pairs
+ * of steps, the state read and written once per pass), so no instance ever
+ * waits on another
  * and the launch needs no co-residency. Workgroups take instances longest
  * first.
  *

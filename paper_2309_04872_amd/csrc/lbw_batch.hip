@@ -31,6 +31,15 @@ using namespace lbw;
 namespace {
 
 constexpr int MAX_INST = 65536;
+// Steps per pass of the batched kernel after the first step (temporal
+// blocking). Measured on the 256-instance scan (1024 threads, per step): 112.3
+// us with one step per pass, 73.1 with 2, 54.6 with 4, 44.2 with 8, 42.5 with
+// 16: the longest warm-closure instance bounds the launch, and each pass over
+// one of its tiles pays a memory round trip that the deeper pass shares.
+#ifndef LBW_BATCH_DEPTH
+#define LBW_BATCH_DEPTH 16
+#endif
+constexpr int BATCH_DEPTH = LBW_BATCH_DEPTH;
 constexpr int PAD = 64;  // node padding of every plane (one wavefront)
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -67,7 +76,7 @@ struct BatchArgs {
 // pass (its nodes plus one ring node on each side).
 template <int T, int CPT> struct Lds {
     double g[3][T * CPT];
-    double xc[4][2][T * CPT];  // two-step pass: post-collision +z / -z populations
+    double xc[4][2][T * CPT];  // multi-step pass: post-collision +z / -z populations
     int bad;
 };
 
@@ -217,33 +226,37 @@ __device__ __forceinline__ void step_pass(const BInst &P, const double *src, dou
     __syncthreads();  // the next pass reuses the LDS slots
 }
 
-// Two steps in one pass (temporal blocking). Slot r of the T*CPT slots holds
-// node fix(base - 3 + r) (the copy or wrap rule of the boundary): step t runs
-// on slots [1, NS - 1), its post-collision +z / -z populations go through LDS,
-// and step t + 1 runs on the own slots [3, NS - 3), i.e. nodes
-// [base, base + NS - 6). Populations, E_z and lagged values are read once and
-// written once per two steps; E_z and the lagged values are read from one
-// buffer and written to the other, because the ring slots read values that a
-// neighbouring pass of the same sweep updates.
-template <int T, int CPT> constexpr int pass2_width() { return T * CPT - 6; }
+// S steps in one pass (temporal blocking). Slot r of the NS = T*CPT slots
+// holds node fix(base - (2S - 1) + r) (the copy or wrap rule of the
+// boundary): step 0 of the pass runs on slots [1, NS - 1); each later step m
+// takes its +z / -z populations from the previous one through LDS (the rest
+// population, E_z and the lagged values stay in registers), recovers on
+// slots [2m, NS - 2m) and collides on [2m + 1, NS - 2m - 1), so the last step
+// writes the own slots, nodes [base, base + NS - 4S + 2). Populations, E_z and
+// lagged values are read once and written once per S steps; E_z and the
+// lagged values are read from one buffer and written to the other, because
+// the ring slots read values that a neighbouring pass of the same sweep
+// updates.
+template <int T, int CPT, int S> constexpr int passs_width() { return T * CPT - 4 * S + 2; }
 
-template <int CL, int T, int CPT>
-__device__ __forceinline__ void step_pass2(const BInst &P, const double *src, double *dst, const double *ez_in,
+template <int CL, int T, int CPT, int S>
+__device__ __forceinline__ void step_passs(const BInst &P, const double *src, double *dst, const double *ez_in,
                                            double *ez_out, const double *lag_in, double *lag_out, int base,
                                            long step, Lds<T, CPT> &sh)
 {
     constexpr int K = NScal<1, CL>::K;
     constexpr int NS = T * CPT;
+    static_assert(S >= 2 && passs_width<T, CPT, S>() > 0, "pass depth");
     const int tid = threadIdx.x;
     const int nz = P.nz, bc = P.bc;
     const size_t nzp = (size_t)P.nzp;
     const double dt = P.dt;
-    const int off = base - 3;  // node of slot 0 before the boundary rule
+    const int off = base - (2 * S - 1);  // node of slot 0 before the boundary rule
     // LDS slot of the node next to slot r's node (r's node is fix(off + r))
     auto nb = [&](int r, int d) {
         return bc == BC_PERIODIC ? r + d : map_node(fix_node(off + r, nz, bc) + d, nz, bc) - off;
     };
-    // ---- step t on every slot: pull, E_z, lagged values, recovery into LDS
+    // ---- step 0 on every slot: pull, E_z, lagged values, recovery into LDS
     Node1<CL> nd[CPT];
     double ezv[CPT], lgv[CPT][3];
 #pragma unroll
@@ -257,7 +270,7 @@ __device__ __forceinline__ void step_pass2(const BInst &P, const double *src, do
 #pragma unroll
     for (int j = 0; j < CPT; ++j) recover_node<CL, T, CPT>(P, nd[j], sh, tid + j * T);
     __syncthreads();
-    double rest[CPT][K], lagt[CPT][3];
+    double rest[CPT][K];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int r = tid + j * T;
@@ -266,7 +279,10 @@ __device__ __forceinline__ void step_pass2(const BInst &P, const double *src, do
         Node1<CL> &v = nd[j];
         const double jb = driver_density<1>(P.drv, z * P.delta, 0.0, (step - 0.5) * dt);
         ezv[j] = ezv[j] + dt * (v.A[0] * v.uz + jb);
-        force_collide<CL, T, CPT>(P, v, ezv[j], lgv[j], false, lagt[j], sh, nb(r, 1), nb(r, -1));
+        double lnew[3];
+        force_collide<CL, T, CPT>(P, v, ezv[j], lgv[j], false, lnew, sh, nb(r, 1), nb(r, -1));
+#pragma unroll
+        for (int g = 0; g < 3; ++g) lgv[j][g] = lnew[g];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             rest[j][k] = v.s[k][0];
@@ -274,48 +290,65 @@ __device__ __forceinline__ void step_pass2(const BInst &P, const double *src, do
             sh.xc[k][1][r] = v.s[k][2];
         }
     }
-    __syncthreads();  // movers in LDS; every step-t value of g has been read
-    // ---- step t + 1: pull from LDS on slots [2, NS - 2), recovery into LDS
+    __syncthreads();  // movers in LDS; every value of g has been read
+    // ---- steps 1 .. S - 1
+    for (int m = 1; m < S; ++m) {
+        // pull from LDS on slots [2m, NS - 2m), recovery into LDS
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int r = tid + j * T;
-        if (r < 2 || r >= NS - 2) continue;
-        Node1<CL> &v = nd[j];
-        const int rm = nb(r, -1), rp = nb(r, 1);  // sources of +z and -z movers
+        for (int j = 0; j < CPT; ++j) {
+            const int r = tid + j * T;
+            if (r < 2 * m || r >= NS - 2 * m) continue;
+            Node1<CL> &v = nd[j];
+            const int rm = nb(r, -1), rp = nb(r, 1);  // sources of +z and -z movers
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            v.s[k][0] = rest[j][k];
-            v.s[k][1] = sh.xc[k][0][rm];
-            v.s[k][2] = sh.xc[k][1][rp];
-            double acc = 0.0;
+            for (int k = 0; k < K; ++k) {
+                v.s[k][0] = rest[j][k];
+                v.s[k][1] = sh.xc[k][0][rm];
+                v.s[k][2] = sh.xc[k][1][rp];
+                double acc = 0.0;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) acc += v.s[k][q];
-            v.A[k] = 0.0 + acc;
+                for (int q = 0; q < 3; ++q) acc += v.s[k][q];
+                v.A[k] = 0.0 + acc;
+            }
+            recover_node<CL, T, CPT>(P, v, sh, r);
         }
-        recover_node<CL, T, CPT>(P, v, sh, r);
-    }
-    __syncthreads();
+        __syncthreads();  // g visible; every mover has been read
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        const int r = tid + j * T;
-        const int z = off + r;
-        if (r < 3 || r >= NS - 3 || z >= nz) continue;
-        Node1<CL> &v = nd[j];
-        const double jb = driver_density<1>(P.drv, z * P.delta, 0.0, (step + 0.5) * dt);
-        const double Ez = ezv[j] + dt * (v.A[0] * v.uz + jb);
-        double lnew[3];
-        force_collide<CL, T, CPT>(P, v, Ez, lagt[j], false, lnew, sh, nb(r, 1), nb(r, -1));
-        ez_out[z] = Ez;
-        if constexpr (CL == WARMC) {
+        for (int j = 0; j < CPT; ++j) {
+            const int r = tid + j * T;
+            if (r < 2 * m + 1 || r >= NS - 2 * m - 1) continue;
+            const int z = fix_node(off + r, nz, bc);
+            Node1<CL> &v = nd[j];
+            const double jb = driver_density<1>(P.drv, z * P.delta, 0.0, (step + m - 0.5) * dt);
+            ezv[j] = ezv[j] + dt * (v.A[0] * v.uz + jb);
+            double lnew[3];
+            force_collide<CL, T, CPT>(P, v, ezv[j], lgv[j], false, lnew, sh, nb(r, 1), nb(r, -1));
+            if (m < S - 1) {
 #pragma unroll
-            for (int g = 0; g < 3; ++g) lag_out[(size_t)g * nzp + z] = lnew[g];
+                for (int g = 0; g < 3; ++g) lgv[j][g] = lnew[g];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    rest[j][k] = v.s[k][0];
+                    sh.xc[k][0][r] = v.s[k][1];
+                    sh.xc[k][1][r] = v.s[k][2];
+                }
+            } else {
+                const int zo = off + r;
+                if (zo < nz) {
+                    ez_out[zo] = ezv[j];
+                    if constexpr (CL == WARMC) {
+#pragma unroll
+                        for (int g = 0; g < 3; ++g) lag_out[(size_t)g * nzp + zo] = lnew[g];
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + zo] = v.s[k][q];
+                }
+            }
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + z] = v.s[k][q];
+        __syncthreads();  // movers in LDS (or the pass done); every value of g has been read
     }
-    __syncthreads();  // the next pass reuses the LDS slots
 }
 
 // Finish: stream f*^{n-1} into f^n, E^n = E^{n-1} + dt (n u + n_b) at
@@ -358,7 +391,8 @@ template <int CL, int T, int CPT>
 __device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds<T, CPT> &sh)
 {
     constexpr int W = pass_width<T, CPT>();
-    constexpr int W2 = pass2_width<T, CPT>();
+    constexpr int W2 = passs_width<T, CPT, 2>();
+    constexpr int WD = passs_width<T, CPT, BATCH_DEPTH>();
     constexpr int WF = T * CPT;  // finish passes own every slot
     const int nsteps = a.nsteps;
     int cur = st->cur, ec = st->ecur;
@@ -368,10 +402,11 @@ __device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds
     double *pop[2] = {a.pop0 + P.pop, a.pop1 + P.pop};
     double *ez[2] = {a.ez + P.fld, a.ez + P.fld + nzp};
     double *lag[2] = {a.lag + P.lag, a.lag + P.lag + (CL == WARMC ? NLAG1 * nzp : 0)};
-    // schedule: the first step from the canonical state, then pairs of steps
-    // in two-step passes, then a last single step if one is left. Every pass
-    // ends on a barrier, so each step's stores are visible to the whole
-    // workgroup before the next step reads its neighbours.
+    // schedule: the first step from the canonical state, then passes of
+    // BATCH_DEPTH steps, pairs of steps for what is left, then a last single
+    // step if one is left. Every pass ends on a barrier, so each step's stores
+    // are visible to the whole workgroup before the next step reads its
+    // neighbours.
     long s = 0;
     if (nsteps > 0) {
         for (int base = 0; base < P.nz; base += W)
@@ -380,10 +415,17 @@ __device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds
         cur ^= 1;
         s = 1;
     }
-    for (; s + 2 <= nsteps; s += 2) {
+    for (; s > 0 && s + BATCH_DEPTH <= nsteps; s += BATCH_DEPTH) {
+        for (int base = 0; base < P.nz; base += WD)
+            step_passs<CL, T, CPT, BATCH_DEPTH>(P, pop[cur], pop[cur ^ 1], ez[ec], ez[ec ^ 1], lag[ec],
+                                                lag[ec ^ 1], base, step0 + s, sh);
+        cur ^= 1;
+        ec ^= 1;
+    }
+    for (; s > 0 && s + 2 <= nsteps; s += 2) {
         for (int base = 0; base < P.nz; base += W2)
-            step_pass2<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez[ec], ez[ec ^ 1], lag[ec], lag[ec ^ 1], base,
-                                   step0 + s, sh);
+            step_passs<CL, T, CPT, 2>(P, pop[cur], pop[cur ^ 1], ez[ec], ez[ec ^ 1], lag[ec], lag[ec ^ 1], base,
+                                      step0 + s, sh);
         cur ^= 1;
         ec ^= 1;
     }
@@ -792,14 +834,16 @@ lbw_status lbw_batch_step(lbw_batch *b, int nsteps, int use_graph)
     if (rc != LBW_OK) return rc;
     BHIPCHK(b, hipEventRecord(b->ev[1], b->stream));
     b->ev_recorded = true;
-    // the launch's schedule (run_instance): one single step, (nsteps - 1) / 2
-    // two-step sweeps, one more single step if nsteps - 1 is odd, the finish;
-    // each sweep and the finish swap the population buffers, each two-step
-    // sweep swaps the E_z / lagged-value buffers
-    const int pairs = (nsteps - 1) / 2, single_tail = (nsteps - 1) % 2;
+    // the launch's schedule (run_instance): one single step, (nsteps - 1) /
+    // BATCH_DEPTH deep sweeps, then two-step sweeps and one more single step
+    // for the remainder, the finish; each sweep and the finish swap the
+    // population buffers, each multi-step sweep swaps the E_z / lagged-value
+    // buffers
+    const int deep = (nsteps - 1) / BATCH_DEPTH, tail = (nsteps - 1) % BATCH_DEPTH;
+    const int pairs = tail / 2, single_tail = tail % 2;
     b->step += nsteps;
-    b->cur ^= (1 + pairs + single_tail + 1) & 1;
-    b->ecur ^= pairs & 1;
+    b->cur ^= (1 + deep + pairs + single_tail + 1) & 1;
+    b->ecur ^= (deep + pairs) & 1;
     return LBW_OK;
 }
 
