@@ -314,6 +314,45 @@ def test_split_steps_and_checkpoint_bitwise(closure, dims):
     assert c.step_count == 12
 
 
+@pytest.mark.parametrize("bc", ["open", "periodic"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_deep_passes_bitwise_1d(storage, bc):
+    """The persistent 1D kernel's passes of many local-equilibrium steps equal
+    single steps bit for bit: 100 steps in one call (the first step, four
+    passes of 24, a pair and a single step, in one launch) against 48 steps in
+    1-, 2- and 5-step calls followed by one 52-step call, and against 40 + 60
+    steps across a checkpoint reload; nz = 1000 gives three 418-node tiles,
+    the last one partial."""
+    from paper_2309_04872_amd.sim import Sim
+
+    nz = 1000
+    d = 2 * np.pi / 128
+
+    def fresh():
+        s = Sim(1, nz, delta=d, closure="lec", storage=storage, bc_z=bc)
+        s.init_plasma(0.02, n=workloads.density_noise((1, nz), 1e-3, 5))
+        s.init_driver(0.6, 0.7, z0=4.0)
+        return s
+
+    print("deep passes", storage, bc, flush=True)
+    a = fresh().step(100)
+    b = fresh()
+    for k in (1, 2, 5) * 6:
+        b.step(k)
+    b.step(100 - b.step_count)
+    c = fresh().step(40)
+    blob = c.save_state()
+    c2 = fresh()
+    c2.load_state(blob)
+    c2.step(60)
+    for q in ("n", "uz"):
+        assert np.array_equal(a.read(q), b.read(q)), q
+        assert np.array_equal(a.read(q), c2.read(q)), q
+    assert np.array_equal(a.field("ez"), b.field("ez"))
+    assert np.array_equal(a.field("ez"), c2.field("ez"))
+    assert np.abs(a.read("uz")).max() > 1e-3
+
+
 @pytest.mark.parametrize("closure", ["lec", "warmc"])
 def test_diagnostics_parity(closure):
     nz, nx = 128, 32
