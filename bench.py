@@ -153,6 +153,35 @@ def batch_bytes_per_step(insts):
 BATCH_TRAFFIC_PER_STEP = 33.55e6
 
 
+def sequential_fp64(insts, steps):
+    """The same scan as plain single runs: every instance as its own 1D FP64
+    simulation (lbw_create / lbw_step), one after another on the GPU; only the
+    lbw_step calls are timed (HIP events), so allocation and initialisation
+    stay outside."""
+    import torch
+
+    from paper_2309_04872_amd.sim import Sim
+
+    total_ms = 0.0
+    for d in insts:
+        delta = 2 * np.pi / 128
+        s = Sim(1, d["nz"], delta=delta, dt=0.1 * delta, tau_tilde=0.52, closure=d["closure"], dvel=1.0)
+        s.init_plasma(d["mu"])
+        if d["alpha"] != 0.0:
+            s.init_driver(d["alpha"], d["sigma_z"], z0=6.0 * d["sigma_z"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        s.close()
+    cells = sum(d["nz"] for d in insts)
+    return {"value": cells * steps / (total_ms / 1e3) / 1e6, "unit": "MLUPS", "seconds": total_ms / 1e3,
+            "kind": "single FP64 runs in sequence (lbw_step per instance)"}
+
+
 def cpu_baseline_batch(insts, budget_s=12.0):
     """The CPU oracle on a bounded sample of the scan: its first instances in
     turn (alternating closures), 256 steps each, until the budget is spent."""
@@ -260,6 +289,7 @@ def bench_batch(args):
         },
         "wall_s": wall,
         "diagnostics": {"nonfinite_instances": int((bad > 0).sum())},
+        "sequential_fp64": sequential_fp64(insts, steps),
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_batch(insts, args.cpu_budget)
