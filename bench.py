@@ -144,6 +144,57 @@ def cpu_baseline(w, budget_s=12.0):
                       f"{n1} steps on one thread ({dt1:.1f} s)"}
 
 
+def cpu_baseline_adjoint(cfg, weights, budget_s=12.0):
+    """The CPU oracle's route to the same gradient: central differences over
+    the 64 slice weights need 2 x 64 forward runs of the whole workload. A
+    bounded sample of one forward run (the full grid with the sliced driver,
+    as many steps as fit the budget) is timed; the gradient rate is that
+    forward rate over 128."""
+    import oracle
+
+    o = oracle.Oracle(2, cfg["nz"], cfg["nx"], delta=cfg["delta"], dt=cfg["dt"], tau_tilde=cfg["tau_tilde"],
+                      closure=0, dvel=3.0, mu=cfg["mu"], alpha=cfg["alpha"], sigma_z=cfg["sigma_z"],
+                      sigma_x=cfg["sigma_x"], z0=cfg["z0"], slice_w=weights, slice_zmin=cfg["slice_zmin"],
+                      slice_zmax=cfg["slice_zmax"])
+    o.init()
+    o.step(1)
+    cells = cfg["nz"] * cfg["nx"]
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        o.step(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    fwd = cells * n / dt / 1e6
+    return {"value": fwd / 128, "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "forward_mlups": fwd,
+            "sample": f"full {cfg['nx']}x{cfg['nz']} grid with the sliced driver, {n} FP64 forward steps "
+                      f"({dt:.1f} s); a central-difference gradient over 64 slices takes 128 forward runs"}
+
+
+def fd_fp64_gpu(cfg, weights):
+    """The plain FP64 route on the GPU: central differences over the 64 slices
+    with FP64 forward runs. One 2000-step FP64 forward run is timed (HIP
+    events around lbw_step) and scaled by the 128 runs a gradient needs."""
+    import torch
+
+    from paper_2309_04872_amd import adjoint
+
+    c = dict(cfg, storage="fp64")
+    r = adjoint._Run(c, weights).start()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r.sim.step(c["steps"])
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_s = e0.elapsed_time(e1) / 1e3
+    r.sim.close()
+    cells = c["nz"] * c["nx"]
+    return {"value": cells * c["steps"] / (128 * fwd_s) / 1e6, "unit": "MLUPS", "forward_s": fwd_s, "runs": 128,
+            "kind": "central differences of FP64 forward runs on the GPU (one run timed, x 128)"}
+
+
 def batch_bytes_per_step(insts):
     """Algorithmic bytes of one step of the batched scan: per instance
     bytes_per_lu(1, closure, FP64) times its node count."""
@@ -360,7 +411,10 @@ def bench_adjoint(args):
         "wall_s": wall,
         "phases_ms": tm,
         "loss": loss, "grad_norm": float(np.linalg.norm(g)),
+        "fd_fp64": fd_fp64_gpu(cfg, w),
     }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_adjoint(cfg, w, args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 
