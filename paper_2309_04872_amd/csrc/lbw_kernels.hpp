@@ -26,6 +26,7 @@ struct StepArgs {
     const double *ez_in, *ex_in, *by_in;
     double *ez_out, *ex_out, *by_out;
     double *lag;                 // warm closure lagged values, [NLAG][ncell], in place
+    double *lag_alt;             // 1D warm closure: the other lagged-value buffer (multi-step passes)
     unsigned int *fallbacks;     // LEC recovery fallback counter
     const double *aref;          // per-scalar storage reference A_ref (device, K values)
     int nz, nx, ncell;
@@ -575,19 +576,22 @@ __global__ __launch_bounds__(TZ) void k_step1d(StepArgs a)
     step1d_tile<CL, ST, TZ>(a, blockIdx.x, s_g);
 }
 
-// S local-equilibrium 1D steps in one pass over a tile (temporal blocking).
-// Slot r of the TZ threads holds node fix(z0 - (2S - 1) + r) under the
-// boundary rule. Step 0 of the pass recovers every slot and collides on
-// slots [1, TZ - 1); each later step m pulls its +z / -z populations from the
-// previous step's through LDS (rounded to the storage type as a store and
-// reload would round them), recovers on slots [2m, TZ - 2m) and collides on
-// [2m + 1, TZ - 2m - 1), so step S - 1 writes nodes [z0, z0 + TZ - 4S + 2).
-// The per-node arithmetic is that of step1d_tile, so a pass equals S single
-// steps bit for bit. Input: the mid-step state of the step before the pass
-// (pull); E_z read from ez_in, written to ez_out.
+// S 1D steps in one pass over a tile (temporal blocking). Slot r of the TZ
+// threads holds node fix(z0 - (2S - 1) + r) under the boundary rule. Step 0
+// of the pass recovers every slot and collides on slots [1, TZ - 1); each
+// later step m pulls its +z / -z populations from the previous step's
+// through LDS (rounded to the storage type as a store and reload would round
+// them), recovers on slots [2m, TZ - 2m) and collides on [2m + 1, TZ - 2m - 1),
+// so step S - 1 writes nodes [z0, z0 + TZ - 4S + 2). E_z and the warm
+// closure's lagged values stay in registers; the lagged values are read from
+// a.lag and written to a.lag_alt (ring slots read values that a neighbouring
+// tile of the same pass rewrites). The per-node arithmetic is that of
+// step1d_tile, so a pass equals S single steps bit for bit. Input: the
+// mid-step state of the step before the pass (pull); E_z read from ez_in,
+// written to ez_out.
 template <int TZ, int S> constexpr int multi_width() { return TZ - 4 * S + 2; }
 
-template <class ST, int TZ, int S>
+template <int CL, class ST, int TZ, int S>
 __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double (*s_g)[TZ + 2],
                                              typename Store<ST>::ct (*xc)[2][TZ])
 {
@@ -595,7 +599,7 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
     using L = Lattice<1>;
     using CT = typename Store<ST>::ct;
     constexpr int Q = L::Q;
-    constexpr int K = NScal<1, LEC>::K;
+    constexpr int K = NScal<1, CL>::K;
     const int tid = threadIdx.x;
     const int nz = a.nz, bcz = a.bcz;
     const size_t nc = (size_t)a.ncell;
@@ -619,18 +623,41 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
             A[k] = aref[k] + (double)acc;
         }
     };
+    WarmRec w;  // warm closure: the recovered node
     auto recover = [&](const double *A, int r, double &uz) {
-        LecRec l;
-        if (!lec_recover(A[0], A[1], 0.0, a.a_lec, a.dcode, a.two_over_d, l)) {
-            if (a.fallbacks) atomicAdd(a.fallbacks, 1u);
+        if constexpr (CL == LEC) {
+            LecRec l;
+            if (!lec_recover(A[0], A[1], 0.0, a.a_lec, a.dcode, a.two_over_d, l)) {
+                if (a.fallbacks) atomicAdd(a.fallbacks, 1u);
+            }
+            uz = l.uz;
+            s_g[0][r] = l.phi;
+        } else {
+            warm_recover<1>(A, w);
+            uz = w.uz;
+            s_g[0][r] = w.th0z;
+            s_g[1][r] = w.thzz;
+            s_g[2][r] = w.luz;
         }
-        uz = l.uz;
-        s_g[0][r] = l.phi;
     };
-    auto force_collide = [&](CT (*s)[Q], const double *A, double uz, double Ez, int r) {
+    // forcing with the lagged values lg (replaced by this step's) and collision
+    auto force_collide = [&](CT (*s)[Q], const double *A, double uz, double Ez, int r, double *lg) {
+        const int rp = nb(r, 1), rm = nb(r, -1);
+        auto Dz = [&](int g) { return (s_g[g][rp] - s_g[g][rm]) * a.inv2d; };
         double F[K];
         F[0] = 0.0;
-        F[1] = -a.mu * ((s_g[0][nb(r, 1)] - s_g[0][nb(r, -1)]) * a.inv2d) - A[0] * Ez;
+        if constexpr (CL == LEC) {
+            F[1] = -a.mu * Dz(0) - A[0] * Ez;
+        } else {
+            const double n = A[0];
+            const double th0z = w.th0z, thzz = w.thzz, luz = w.luz, th00 = w.th00;
+            const double l00 = lg[0], l0z = lg[1], lluz = lg[2];
+            lg[0] = th00; lg[1] = th0z; lg[2] = luz;
+            const double idt = 1.0 / dt;
+            F[1] = -(th00 - l00) * idt - Dz(0) - n * (Ez * uz);
+            F[2] = -(th0z - l0z) * idt - Dz(1) - n * Ez;
+            F[3] = -2.0 * th0z * ((luz - lluz) * idt) - 2.0 * thzz * Dz(2) - 2.0 * (Ez * th0z);
+        }
         collide_all<1, K, CT>(s, A, aref, F, uz, 0.0, a.lam, a.omega, dt);
     };
     auto rnd = [](CT v) { return (CT)Store<ST>::rnd(v); };
@@ -646,6 +673,11 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
         for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
     }
     double Ez = a.ez_in[z];
+    double lg[3] = {0.0, 0.0, 0.0};
+    if constexpr (CL == WARMC) {
+#pragma unroll
+        for (int g = 0; g < 3; ++g) lg[g] = a.lag[g * nc + z];
+    }
     moments(s, A);
     recover(A, tid, uz);
     __syncthreads();
@@ -653,7 +685,7 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
     if (tid >= 1 && tid < TZ - 1) {
         const double jb = driver_density<1>(a.drv, z * a.delta, 0.0, (a.step - 0.5) * dt);
         Ez = Ez + dt * (A[0] * uz + jb);
-        force_collide(s, A, uz, Ez, tid);
+        force_collide(s, A, uz, Ez, tid, lg);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             rest[k] = rnd(s[k][0]);
@@ -661,7 +693,7 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
             xc[k][1][tid] = rnd(s[k][2]);
         }
     }
-    __syncthreads();  // movers in LDS; every value of phi has been read
+    __syncthreads();  // movers in LDS; every recovered value in LDS has been read
     // ---- steps 1 .. S - 1: pull from LDS, recovery, collision
     for (int m = 1; m < S; ++m) {
         if (tid >= 2 * m && tid < TZ - 2 * m) {
@@ -675,12 +707,12 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
             moments(s, A);
             recover(A, tid, uz);
         }
-        __syncthreads();  // phi visible; every mover has been read
+        __syncthreads();  // recovered values visible; every mover has been read
         if (tid >= 2 * m + 1 && tid < TZ - 2 * m - 1) {
             const int zm = fix_node(off + tid, nz, bcz);
             const double jb = driver_density<1>(a.drv, zm * a.delta, 0.0, (a.step + m - 0.5) * dt);
             Ez = Ez + dt * (A[0] * uz + jb);
-            force_collide(s, A, uz, Ez, tid);
+            force_collide(s, A, uz, Ez, tid, lg);
             if (m < S - 1) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
@@ -692,6 +724,10 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
                 const int zo = off + tid;
                 if (zo < nz) {
                     a.ez_out[zo] = Ez;
+                    if constexpr (CL == WARMC) {
+#pragma unroll
+                        for (int g = 0; g < 3; ++g) a.lag_alt[g * nc + zo] = lg[g];
+                    }
 #pragma unroll
                     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -699,7 +735,7 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
                 }
             }
         }
-        __syncthreads();  // movers in LDS (or the tile done); every value of phi has been read
+        __syncthreads();  // movers in LDS (or the tile done); every recovered value has been read
     }
 }
 
@@ -715,11 +751,19 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
 #define LBW_PERSIST_DEPTH 24
 #endif
 constexpr int PERSIST_DEPTH = LBW_PERSIST_DEPTH;
-__host__ __device__ inline int persist_passes(int closure, int nsteps)
+__host__ __device__ inline int persist_passes(int nsteps)
 {
-    if (closure != LEC || nsteps <= 1) return nsteps;
+    if (nsteps <= 1) return nsteps;
     const int rest = nsteps - 1, tail = rest % PERSIST_DEPTH;
     return 1 + rest / PERSIST_DEPTH + tail / 2 + (tail & 1);
+}
+// Multi-step passes among them: each swaps the warm closure's lagged-value
+// buffers once.
+__host__ __device__ inline int persist_multi_passes(int nsteps)
+{
+    if (nsteps <= 1) return 0;
+    const int rest = nsteps - 1;
+    return rest / PERSIST_DEPTH + (rest % PERSIST_DEPTH) / 2;
 }
 
 // All steps of one lbw_step call in one cooperative launch (1D grids small
@@ -733,11 +777,11 @@ __global__ __launch_bounds__(TZ) void k_step1d_persist(StepArgs a, int nsteps)
     using CT = typename Store<ST>::ct;
     constexpr int NG = CL == LEC ? 1 : 3;
     __shared__ double s_g[NG][TZ + 2];
-    __shared__ CT s_xc[CL == LEC ? 2 : 1][2][CL == LEC ? TZ : 1];
+    __shared__ CT s_xc[NScal<1, CL>::K][2][TZ];
     const int ntiles = (a.nz + TZ - 1) / TZ;
     const int ntiles2 = (a.nz + multi_width<TZ, 2>() - 1) / multi_width<TZ, 2>();
     const int ntilesd = (a.nz + multi_width<TZ, PERSIST_DEPTH>() - 1) / multi_width<TZ, PERSIST_DEPTH>();
-    int t = 0, pass = 0;
+    int t = 0, pass = 0, lp = 0;  // lp: the warm closure's current lagged values are in a.lag_alt
     while (t < nsteps) {
         StepArgs b = a;
         if (pass & 1) {
@@ -746,21 +790,25 @@ __global__ __launch_bounds__(TZ) void k_step1d_persist(StepArgs a, int nsteps)
             b.ez_in = a.ez_out;
             b.ez_out = (double *)a.ez_in;
         }
+        if (lp) {
+            b.lag = a.lag_alt;
+            b.lag_alt = a.lag;
+        }
         if (t > 0) {
             b.do_pull = 1;
             b.do_maxwell = 1;
             b.lag_init = 0;
         }
         b.step = a.step + t;
-        if (CL == LEC && t > 0 && nsteps - t >= PERSIST_DEPTH) {
-            if constexpr (CL == LEC)
-                for (int tile = blockIdx.x; tile < ntilesd; tile += gridDim.x)
-                    step1d_multi<ST, TZ, PERSIST_DEPTH>(b, tile, s_g, s_xc);
+        if (t > 0 && nsteps - t >= PERSIST_DEPTH) {
+            for (int tile = blockIdx.x; tile < ntilesd; tile += gridDim.x)
+                step1d_multi<CL, ST, TZ, PERSIST_DEPTH>(b, tile, s_g, s_xc);
             t += PERSIST_DEPTH;
-        } else if (CL == LEC && t > 0 && nsteps - t >= 2) {
-            if constexpr (CL == LEC)
-                for (int tile = blockIdx.x; tile < ntiles2; tile += gridDim.x) step1d_multi<ST, TZ, 2>(b, tile, s_g, s_xc);
+            lp ^= 1;
+        } else if (t > 0 && nsteps - t >= 2) {
+            for (int tile = blockIdx.x; tile < ntiles2; tile += gridDim.x) step1d_multi<CL, ST, TZ, 2>(b, tile, s_g, s_xc);
             t += 2;
+            lp ^= 1;
         } else {
             for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) step1d_tile<CL, ST, TZ>(b, tile, s_g);
             t += 1;

@@ -103,7 +103,7 @@ int nlag(int dims, int closure) { return closure == LBW_WARMC ? (dims == 1 ? NLA
 size_t storage_size(int storage) { return storage == LBW_FP64 ? 8 : (storage == LBW_FP32 ? 4 : 2); }
 
 struct Layout {
-    size_t pop[2], fld[2][3], lag, stage, part, aref, slice, fallbacks, diag, total;
+    size_t pop[2], fld[2][3], lag, lag_alt, stage, part, aref, slice, fallbacks, diag, total;
     int K, Q, nblk_diag;
 };
 
@@ -145,6 +145,10 @@ Layout make_layout(const lbw_grid_desc *g)
     for (int b = 0; b < 2; ++b)
         for (int f = 0; f < 3; ++f) { L.fld[b][f] = off; off += align_up(nc * 8); }
     L.lag = off; off += align_up(nc * 8 * (size_t)nlag(g->dims, g->closure));
+    // 1D warm closure: a second buffer, which the multi-step passes of the
+    // persistent kernel write while their ring slots still read the first
+    L.lag_alt = L.lag;
+    if (g->dims == 1 && g->closure == LBW_WARMC) { L.lag_alt = off; off += align_up(nc * 8 * (size_t)NLAG1); }
     const int ks = L.K > 3 ? L.K : 3;
     L.stage = off; off += align_up(nc * 8 * (size_t)ks);
     L.nblk_diag = (int)((nc + 255) / 256);
@@ -178,7 +182,10 @@ struct lbw_sim {
     double kernel_ms;
     long launches, pending_launches;
     int persist;  // 1D: workgroups of the persistent kernel (-1: not queried yet, 0: unavailable)
+    int lcur;     // 1D warm closure: the lagged values are in L.lag_alt (1) or L.lag (0)
 };
+
+static char *lag_cur(lbw_sim *s) { return s->ws + (s->lcur ? s->L.lag_alt : s->L.lag); }
 
 static lbw_status fail(lbw_sim *s, lbw_status code, const std::string &m)
 {
@@ -218,7 +225,8 @@ StepArgs base_args(lbw_sim *s)
     a.axi = g.geom == LBW_GEOM_AXI;
     a.aref = (const double *)(s->ws + s->L.aref);
     a.fallbacks = (unsigned int *)(s->ws + s->L.fallbacks);
-    a.lag = g.closure == LBW_WARMC ? (double *)(s->ws + s->L.lag) : nullptr;
+    a.lag = g.closure == LBW_WARMC ? (double *)lag_cur(s) : nullptr;
+    a.lag_alt = g.closure == LBW_WARMC ? (double *)(s->ws + (s->lcur ? s->L.lag : s->L.lag_alt)) : nullptr;
     a.step = s->step;
     a.drv = s->drv;
     return a;
@@ -277,10 +285,10 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_step1d_persist<CL, ST, TZ>, TZ, 0) != hipSuccess)
             return 0;
-        // local equilibrium: passes of S steps run on tiles of TZ - 4S + 2 nodes
+        // passes of S steps run on tiles of TZ - 4S + 2 nodes
         const int t1 = (nz + TZ - 1) / TZ, t2 = (nz + multi_width<TZ, 2>() - 1) / multi_width<TZ, 2>();
         const int td = (nz + multi_width<TZ, PERSIST_DEPTH>() - 1) / multi_width<TZ, PERSIST_DEPTH>();
-        const int ntiles = CL == LEC ? std::max(t1, std::max(t2, td)) : t1;
+        const int ntiles = std::max(t1, std::max(t2, td));
         const int maxg = per * cus;
         return ntiles < maxg ? ntiles : maxg;
     }
@@ -445,6 +453,7 @@ lbw_status lbw_create(const lbw_grid_desc *grid, void *ws, size_t ws_bytes, void
     s->launches = 0;
     s->pending_launches = 0;
     s->persist = -1;
+    s->lcur = 0;
     *out = s;
     return LBW_OK;
 }
@@ -514,6 +523,7 @@ static lbw_status reset_common(lbw_sim *s, double mu)
         HIPCHK(s, hipMemsetAsync(s->ws + s->L.lag, 0, s->L.stage - s->L.lag, s->stream));
     HIPCHK(s, hipMemsetAsync(s->ws + s->L.fallbacks, 0, 8, s->stream));
     s->pcur = s->fcur = 0;
+    s->lcur = 0;
     s->canonical = true;
     s->lag_valid = false;
     s->step = 0;
@@ -701,9 +711,10 @@ lbw_status lbw_step(lbw_sim *s, int nsteps)
         a.do_maxwell = s->canonical ? 0 : 1;
         a.lag_init = s->lag_valid ? 0 : 1;
         HIPCHK(s, ops.step_persist(a, nsteps, s->persist, s->stream));
-        const int passes = persist_passes(s->g.closure, nsteps);  // buffer swaps
+        const int passes = persist_passes(nsteps);  // buffer swaps
         s->pcur ^= passes & 1;
         s->fcur ^= passes & 1;
+        if (s->g.closure == LBW_WARMC) s->lcur ^= persist_multi_passes(nsteps) & 1;
         s->canonical = false;
         s->lag_valid = true;
         s->step += nsteps;
@@ -860,7 +871,7 @@ lbw_status lbw_save_state(lbw_sim *s, void *host, size_t bytes)
     for (int f = 0; f < 3; ++f, p += nc * 8)
         HIPCHK(s, hipMemcpyAsync(p, s->ws + s->L.fld[s->fcur][f], nc * 8, hipMemcpyDeviceToHost, s->stream));
     const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
-    if (lagb) HIPCHK(s, hipMemcpyAsync(p, s->ws + s->L.lag, lagb, hipMemcpyDeviceToHost, s->stream));
+    if (lagb) HIPCHK(s, hipMemcpyAsync(p, lag_cur(s), lagb, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     std::memcpy(host, &h, sizeof(h));
     return LBW_OK;
@@ -888,6 +899,7 @@ lbw_status lbw_load_state(lbw_sim *s, const void *host, size_t bytes)
     for (int f = 0; f < 3; ++f, p += nc * 8)
         HIPCHK(s, hipMemcpyAsync(s->ws + s->L.fld[0][f], p, nc * 8, hipMemcpyHostToDevice, s->stream));
     const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
+    s->lcur = 0;
     if (lagb) HIPCHK(s, hipMemcpyAsync(s->ws + s->L.lag, p, lagb, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->ws + s->L.fallbacks, &h.fallbacks, 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -934,7 +946,7 @@ lbw_status lbw_save_state_device(lbw_sim *s, void *dev)
         HIPCHK(s, hipMemcpyAsync(p + d.fld[f], s->ws + s->L.fld[s->fcur][f], nc * 8, hipMemcpyDeviceToDevice,
                                  s->stream));
     const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
-    if (lagb) HIPCHK(s, hipMemcpyAsync(p + d.lag, s->ws + s->L.lag, lagb, hipMemcpyDeviceToDevice, s->stream));
+    if (lagb) HIPCHK(s, hipMemcpyAsync(p + d.lag, lag_cur(s), lagb, hipMemcpyDeviceToDevice, s->stream));
     return LBW_OK;
 }
 
@@ -953,6 +965,7 @@ lbw_status lbw_load_state_device(lbw_sim *s, const void *dev, long step)
     for (int f = 0; f < 3; ++f)
         HIPCHK(s, hipMemcpyAsync(s->ws + s->L.fld[0][f], p + d.fld[f], nc * 8, hipMemcpyDeviceToDevice, s->stream));
     const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
+    s->lcur = 0;
     if (lagb) HIPCHK(s, hipMemcpyAsync(s->ws + s->L.lag, p + d.lag, lagb, hipMemcpyDeviceToDevice, s->stream));
     s->step = step;
     s->lag_valid = step > 0;

@@ -367,25 +367,27 @@ def test_split_steps_and_checkpoint_bitwise(closure, dims):
 
 @pytest.mark.parametrize("bc", ["open", "periodic"])
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
-def test_deep_passes_bitwise_1d(storage, bc):
-    """The persistent 1D kernel's passes of many local-equilibrium steps equal
-    single steps bit for bit: 100 steps in one call (the first step, four
-    passes of 24, a pair and a single step, in one launch) against 48 steps in
-    1-, 2- and 5-step calls followed by one 52-step call, and against 40 + 60
-    steps across a checkpoint reload; nz = 1000 gives three 418-node tiles,
-    the last one partial."""
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_deep_passes_bitwise_1d(closure, storage, bc):
+    """The persistent 1D kernel's passes of many steps equal single steps bit
+    for bit: 100 steps in one call (the first step, four passes of 24, a pair
+    and a single step, in one launch) against 48 steps in 1-, 2- and 5-step
+    calls followed by one 52-step call, and against 40 + 60 steps across a
+    checkpoint reload; nz = 1000 gives three 418-node tiles, the last one
+    partial. The warm closure's lagged values alternate between two buffers
+    over the multi-step passes."""
     from paper_2309_04872_amd.sim import Sim
 
     nz = 1000
     d = 2 * np.pi / 128
 
     def fresh():
-        s = Sim(1, nz, delta=d, closure="lec", storage=storage, bc_z=bc)
+        s = Sim(1, nz, delta=d, closure=closure, storage=storage, bc_z=bc)
         s.init_plasma(0.02, n=workloads.density_noise((1, nz), 1e-3, 5))
         s.init_driver(0.6, 0.7, z0=4.0)
         return s
 
-    print("deep passes", storage, bc, flush=True)
+    print("deep passes", closure, storage, bc, flush=True)
     a = fresh().step(100)
     b = fresh()
     for k in (1, 2, 5) * 6:
@@ -396,7 +398,7 @@ def test_deep_passes_bitwise_1d(storage, bc):
     c2 = fresh()
     c2.load_state(blob)
     c2.step(60)
-    for q in ("n", "uz"):
+    for q in ("n", "uz") + (("lambda", "thzz") if closure == "warmc" else ()):
         assert np.array_equal(a.read(q), b.read(q)), q
         assert np.array_equal(a.read(q), c2.read(q)), q
     assert np.array_equal(a.field("ez"), b.field("ez"))
