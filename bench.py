@@ -524,7 +524,7 @@ def main():
         line["roofline"]["note"] = (
             "one cooperative launch runs every step (kernel_avg_us and launches count steps); the 1D "
             "state stays in the L2 cache, so the step is bound by the latency of its recovery chain "
-            "and grid barriers (24 local-equilibrium steps per pass), not by HBM")
+            "and grid barriers (24 steps per pass), not by HBM")
     if paper:
         line["paper_baseline"] = {
             "value": paper, "unit": "MLUPS", "hardware": "96 cores, Intel Xeon E5-2695 @ 2.40 GHz, MPI",
