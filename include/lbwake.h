@@ -215,6 +215,18 @@ size_t lbw_state_device_bytes(const lbw_sim *sim);
 lbw_status lbw_save_state_device(lbw_sim *sim, void *device_dst);
 lbw_status lbw_load_state_device(lbw_sim *sim, const void *device_src, long step);
 
+/* Advance nsteps steps one at a time and record the canonical state after
+ * each: the state after step m (m = 1 .. nsteps of this call) goes to
+ * device_states + (m - 1) * stride, in the layout above (caller-owned device
+ * memory; stride a multiple of 256 and at least lbw_state_device_bytes()).
+ * The records and the simulation's final state equal those of nsteps calls of
+ * lbw_step(sim, 1), each followed by lbw_save_state_device, bit for bit: each
+ * step's closing canonicalisation (streaming and field completion, Sec. 2.1
+ * and Sec. 5) writes its record directly and the next step reads it, so no
+ * state is copied. For checkpoint-and-recompute. Asynchronous on the stream;
+ * not included in lbw_set_timing's kernel timing. */
+lbw_status lbw_step_record(lbw_sim *sim, int nsteps, void *device_states, size_t stride);
+
 /* ---------------------------------------------------------------------------
  * Discrete adjoint of the 2D local-equilibrium step (Sec. 2.2, Sec. 3.1,
  * Sec. 5): the transposed Jacobian of one step of lbw_step, and the

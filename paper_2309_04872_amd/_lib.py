@@ -29,7 +29,7 @@ EXPORTS = [
     "lbw_set_field", "lbw_step", "lbw_read_moment", "lbw_read_moment_device", "lbw_read_field",
     "lbw_diagnostics", "lbw_step_count", "lbw_set_timing", "lbw_get_timing", "lbw_state_bytes", "lbw_save_state", "lbw_load_state",
     "lbw_last_error", "lbw_version", "lbw_destroy",
-    "lbw_state_device_bytes", "lbw_save_state_device", "lbw_load_state_device",
+    "lbw_state_device_bytes", "lbw_save_state_device", "lbw_load_state_device", "lbw_step_record",
     "lbw_adjoint_bytes", "lbw_adjoint_workspace_bytes", "lbw_adjoint_step", "lbw_adjoint_init_fields",
     "lbw_batch_workspace_bytes", "lbw_batch_create", "lbw_batch_init", "lbw_batch_step",
     "lbw_batch_set_config", "lbw_batch_get_config", "lbw_batch_autotune", "lbw_batch_read",
@@ -130,6 +130,8 @@ def load(path: str | None = None):
     L.lbw_version.argtypes = []
     L.lbw_destroy.restype = None
     L.lbw_destroy.argtypes = [vp]
+    L.lbw_step_record.restype = ctypes.c_int
+    L.lbw_step_record.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t]
     L.lbw_state_device_bytes.restype = ctypes.c_size_t
     L.lbw_state_device_bytes.argtypes = [vp]
     L.lbw_save_state_device.restype = ctypes.c_int

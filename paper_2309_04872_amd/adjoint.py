@@ -115,9 +115,7 @@ def loss_and_grad(cfg, weights, every=100, grad_out=1.0, timing=False):
         mark("rec0")
         sim.load_state_device(ckpt[n0], n0)
         sim.save_state_device(buf[0:sb])
-        for m in range(1, n1 - n0 + 1):
-            sim.step(1)
-            sim.save_state_device(buf[m * sb:(m + 1) * sb])
+        sim.step_record(n1 - n0, buf[sb:], sb)
         mark("rec1")
         mark("adj0")
         for n in range(n1 - 1, n0 - 1, -1):

@@ -950,6 +950,66 @@ lbw_status lbw_save_state_device(lbw_sim *s, void *dev)
     return LBW_OK;
 }
 
+lbw_status lbw_step_record(lbw_sim *s, int nsteps, void *dev, size_t stride)
+{
+    if (!s || !dev) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (nsteps < 0) return fail(s, LBW_ERR_ARG, "nsteps must be >= 0");
+    if (((uintptr_t)dev % ALIGN) != 0) return fail(s, LBW_ERR_ARG, "device buffer must be 256-byte aligned");
+    const DevStateLayout d = dev_state_layout(s);
+    if (stride < d.total || stride % ALIGN != 0)
+        return fail(s, LBW_ERR_ARG, "stride must be a multiple of 256 of at least lbw_state_device_bytes()");
+    if (nsteps == 0) return LBW_OK;
+    if (!s->canonical) return fail(s, LBW_ERR_STATE, "state is not canonical");
+    const Ops ops = ops_for(s->g);
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
+    char *base = (char *)dev;
+    double *stage = (double *)(s->ws + s->L.stage);
+    for (int m = 0; m < nsteps; ++m) {
+        // fused step from the canonical state (the simulation's own buffers,
+        // then the previous record) into the workspace's other buffers
+        StepArgs a = base_args(s);
+        set_io(s, a);
+        if (m > 0) {
+            const char *in = base + (size_t)(m - 1) * stride;
+            a.src = in + d.pop;
+            a.ez_in = (const double *)(in + d.fld[0]);
+            a.ex_in = (const double *)(in + d.fld[1]);
+            a.by_in = (const double *)(in + d.fld[2]);
+        }
+        a.do_pull = 0;
+        a.do_maxwell = 0;
+        a.lag_init = s->lag_valid ? 0 : 1;
+        ops.step(a, s->stream);
+        s->lag_valid = true;
+        s->step++;
+        // canonicalisation from the workspace into record m
+        StepArgs f = base_args(s);
+        char *out = base + (size_t)m * stride;
+        f.src = s->ws + s->L.pop[1 - s->pcur];
+        f.dst = out + d.pop;
+        f.ez_in = (const double *)(s->ws + s->L.fld[1 - s->fcur][0]);
+        f.ex_in = (const double *)(s->ws + s->L.fld[1 - s->fcur][1]);
+        f.by_in = (const double *)(s->ws + s->L.fld[1 - s->fcur][2]);
+        f.ez_out = (double *)(out + d.fld[0]);
+        f.ex_out = (double *)(out + d.fld[1]);
+        f.by_out = (double *)(out + d.fld[2]);
+        ops.finish(f, stage, stage + nc, s->stream);
+        if (lagb) HIPCHK(s, hipMemcpyAsync(out + d.lag, lag_cur(s), lagb, hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(s, hipGetLastError());
+    }
+    // the simulation's own canonical buffers take the last record
+    const char *last = base + (size_t)(nsteps - 1) * stride;
+    HIPCHK(s, hipMemcpyAsync(s->ws + s->L.pop[s->pcur], last + d.pop, nc * s->L.K * s->L.Q * storage_size(s->g.storage),
+                             hipMemcpyDeviceToDevice, s->stream));
+    for (int f = 0; f < 3; ++f)
+        HIPCHK(s, hipMemcpyAsync(s->ws + s->L.fld[s->fcur][f], last + d.fld[f], nc * 8, hipMemcpyDeviceToDevice,
+                                 s->stream));
+    s->canonical = true;
+    return LBW_OK;
+}
+
 lbw_status lbw_load_state_device(lbw_sim *s, const void *dev, long step)
 {
     if (!s || !dev) return fail(s, LBW_ERR_ARG, "NULL argument");

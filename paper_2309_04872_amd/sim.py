@@ -174,6 +174,15 @@ class Sim:
         self._check(self._lib.lbw_save_state_device(self._h, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def step_record(self, nsteps, buf, stride=None):
+        """Advance nsteps steps, writing the canonical state after each into
+        ``buf`` (a uint8 device tensor) at offsets 0, stride, 2 stride, ..."""
+        stride = self.state_device_bytes() if stride is None else int(stride)
+        if buf.numel() < nsteps * stride:
+            raise ValueError("buffer too small for the records")
+        self._check(self._lib.lbw_step_record(self._h, int(nsteps), ctypes.c_void_p(buf.data_ptr()), stride))
+        return self
+
     def load_state_device(self, buf, step):
         self._check(self._lib.lbw_load_state_device(self._h, ctypes.c_void_p(buf.data_ptr()), int(step)))
         return self
