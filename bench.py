@@ -51,15 +51,15 @@ def bytes_per_lu(dims, closure, storage):
 # (the summaries and commands are in profiles/k_step2d_*.md). Valid for the
 # kernel as profiled; remove an entry when the kernel changes.
 TRAFFIC_BYTES_PER_LAUNCH = {
-    ("wake2d_lec_fp32", "fp32"): 301.2e6,
-    ("wake2d_lec_fp32", "fp64"): 605.7e6,
-    ("wake2d_warmc", "fp64"): 6685.6e6,
-    ("wake2d_warmc", "fp32"): 3956.2e6,
-    ("wake2d_warmc", "fp16dev"): 2119.4e6,
-    ("wake_axi_lec", "fp64"): 1092.6e6,
-    ("wake_axi_lec", "fp32"): 544.5e6,
-    ("wake_axi_warmc", "fp64"): 3072.3e6,
-    ("wake_axi_warmc", "fp32"): 1600.4e6,
+    ("wake2d_lec_fp32", "fp32"): 301.1e6,
+    ("wake2d_lec_fp32", "fp64"): 605.2e6,
+    ("wake2d_warmc", "fp64"): 6702.9e6,
+    ("wake2d_warmc", "fp32"): 3956.0e6,
+    ("wake2d_warmc", "fp16dev"): 2119.7e6,
+    ("wake_axi_lec", "fp64"): 1092.0e6,
+    ("wake_axi_lec", "fp32"): 544.2e6,
+    ("wake_axi_warmc", "fp64"): 3071.8e6,
+    ("wake_axi_warmc", "fp32"): 1600.6e6,
 }
 
 
