@@ -92,7 +92,7 @@ struct Tile2WarmAxi64 {
     static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1, STRIP = 1;
 };
 constexpr int TZ1 = LBW_TZ1;  // 1D tile, one launch per step
-constexpr int TZP_SMALL = 512, TZP_LARGE = 1024;  // 1D tiles of the persistent kernel
+constexpr int TZP_SMALL = 192, TZP_LARGE = 256;  // 1D tiles of the persistent kernel
 constexpr int MAX_SLICES = 4096;
 constexpr size_t ALIGN = 256;
 
@@ -272,10 +272,15 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
             hipLaunchKernelGGL((k_step1d<CL, ST, TZ1>), grid, dim3(TZ1), 0, st, a);
         }
     }
-    // Tile of the persistent 1D kernel. The grid-wide barrier between steps
-    // costs more the more workgroups take part, so fewer, larger tiles win
-    // (measured per step: 4096 nodes 5.6 / 5.2 / 5.5 us with 256 / 512 / 1024
-    // node tiles; 16384 nodes 10.5 / 7.3 / 6.3 us).
+    // Tile of the persistent 1D kernel. With passes of 24 steps per grid
+    // barrier the latency of a pass's own steps dominates, and it grows with
+    // the waves a workgroup runs per SIMD: small tiles on many compute units
+    // win although their rings redo more work. Measured per step (local
+    // equilibrium / warm closure) at 4096 nodes: 1.97 / 1.32 us with 512-node
+    // tiles, 1.79 / 1.04 with 256, 1.73 / 1.03 with 192, 1.73 / 1.36 with 128;
+    // at 16384 nodes: 2.57 / 2.07 with 1024, 1.99 / 1.43 with 512, 1.85 / 1.45
+    // with 256. (With one step per pass the barrier dominated and large tiles
+    // won: 4096 nodes 5.6 / 5.2 / 5.5 us with 256 / 512 / 1024.)
     static bool persist_large(int nz) { return nz > 8192; }
     template <int TZ> static int persist_grid_t(int nz)
     {

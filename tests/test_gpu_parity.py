@@ -415,7 +415,7 @@ def test_deep_passes_bitwise_1d(closure, storage, bc):
     for bit: 100 steps in one call (the first step, four passes of 24, a pair
     and a single step, in one launch) against 48 steps in 1-, 2- and 5-step
     calls followed by one 52-step call, and against 40 + 60 steps across a
-    checkpoint reload; nz = 1000 gives three 418-node tiles, the last one
+    checkpoint reload; nz = 1000 spans eleven 98-node tiles, the last one
     partial. The warm closure's lagged values alternate between two buffers
     over the multi-step passes."""
     from paper_2309_04872_amd.sim import Sim
