@@ -740,13 +740,13 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
 }
 
 // Passes of the persistent 1D kernel for nsteps steps: the first step from
-// the canonical state as a single step, then (local equilibrium) passes of
-// PERSIST_DEPTH steps, pairs of steps for what is left, and a single step
-// when one is left. Each pass swaps the population and E_z buffers once.
-// Measured per step (4096 / 16384 nodes): 3.10 / 4.51 us with passes of 2
-// steps, 2.41 / 3.70 (4), 2.02 / 2.88 (8), 1.89 / 2.58 (16), 1.83 / 2.48
-// (24), 1.82 / 2.45 (32): past 24 the pass's own step latency dominates and
-// the redundant halo work (4 nodes per step) grows.
+// the canonical state as a single step, then passes of PERSIST_DEPTH steps,
+// pairs of steps for what is left, and a single step when one is left. Each
+// pass swaps the population and E_z buffers once. Measured per step (local
+// equilibrium, 4096 / 16384 nodes, 512 / 1024-node tiles): 3.10 / 4.51 us
+// with passes of 2 steps, 2.41 / 3.70 (4), 2.02 / 2.88 (8), 1.89 / 2.58 (16),
+// 1.83 / 2.48 (24), 1.82 / 2.45 (32): past 24 the pass's own step latency
+// dominates and the redundant halo work (4 nodes per step) grows.
 #ifndef LBW_PERSIST_DEPTH
 #define LBW_PERSIST_DEPTH 24
 #endif
