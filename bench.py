@@ -60,6 +60,9 @@ TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake_axi_lec", "fp32"): 544.2e6,
     ("wake_axi_warmc", "fp64"): 3071.8e6,
     ("wake_axi_warmc", "fp32"): 1600.6e6,
+    ("wake2d_lec_fp32", "fp16dev"): 170.5e6,
+    ("wake_axi_lec", "fp16dev"): 307.6e6,
+    ("wake_axi_warmc", "fp16dev"): 892.7e6,
 }
 
 
