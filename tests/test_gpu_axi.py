@@ -193,3 +193,49 @@ def test_axi_warm_pressure_anisotropy_near_bunch():
     print("max |P_par / P_perp - 1| near the bunch", dev.max(), flush=True)
     assert np.all(np.isfinite(dev))
     assert 0.05 < dev.max() < 0.2
+
+
+def _cone_angle(closure, steps=24000, thr=1e-3):
+    """Angle (degrees) of the front of the density response behind the bunch
+    in the production run: for each radius in [1.5, 5] the point nearest the
+    bunch where |n - 1| exceeds thr of its peak; the distance behind the
+    bunch grows as r / tan(theta)."""
+    from paper_2309_04872_amd.sim import Sim
+
+    w = workloads.workload("wake_axi_" + closure)
+    s = Sim(2, w["nz"], w["nx"], delta=w["delta"], closure=closure, geom="axi")
+    s.init_plasma(w["mu"])
+    s.init_driver(w["alpha"], w["sigma_z"], w["sigma_x"], z0=w["z0"])
+    s.step(steps)
+    dn = np.abs(s.read("n") - 1)
+    z = np.arange(w["nz"]) * w["delta"]
+    r = (np.arange(w["nx"]) + 0.5) * w["delta"]
+    zc = w["z0"] + steps * w["dt"]
+    rs, behind = [], []
+    for j in np.nonzero((r >= 1.5) & (r <= 5.0))[0]:
+        idx = np.nonzero((dn[j] > thr * dn.max()) & (z < zc))[0]
+        if idx.size:
+            rs.append(r[j])
+            behind.append(zc - z[idx.max()])
+    slope = np.polyfit(rs, behind, 1)[0]
+    return np.degrees(np.arctan(1.0 / slope))
+
+
+def test_axi_mach_cones():
+    """Sec. 5, Fig. 5 and 6: the pressure waves trail the bunch in a cone of
+    angle arcsin(c_s), and the warm closure's is the wider one (App. B, eq.
+    sound-speed1/2 at mu = 0.04: c_s = 0.246 and 0.328, 14.3 and 19.1
+    degrees). The front read at 1e-3 of the peak response lags the
+    characteristic (the amplitude decays with r and the lattice diffuses
+    it), so the measured angles sit below those values: 10.4 and 16.1
+    degrees here after 24 000 steps; the ordering is the paper's."""
+    th = {}
+    for closure, cs2 in (("lec", (5.0 / 3.0) * 0.04 / (1 + 2.5 * 0.04)), ("warmc", None)):
+        if cs2 is None:
+            l0 = 0.5 * (3 * 0.04 + np.sqrt(9 * 0.04 ** 2 + 4))
+            cs2 = 0.04 * (3 - 0.04 / l0) / (l0 + 0.04)
+        theory = np.degrees(np.arcsin(np.sqrt(cs2)))
+        th[closure] = _cone_angle(closure)
+        print(closure, "cone angle", th[closure], "theory", theory, flush=True)
+        assert 0.6 * theory < th[closure] < 1.05 * theory
+    assert th["warmc"] > 1.3 * th["lec"]
