@@ -105,6 +105,8 @@ def test_create_validation(lib):
     assert lib.lbw_step_count(h) == 0
     assert lib.lbw_step(h, 1) == -6  # LBW_ERR_STATE: step before init
     assert b"init" in lib.lbw_last_error(h)
+    assert lib.lbw_step_record(h, 1, ctypes.c_void_p(512 * 1024), 1 << 20) == -6
+    assert lib.lbw_step_record(None, 1, ctypes.c_void_p(512 * 1024), 1 << 20) == -1
     lib.lbw_destroy(h)
     assert _create(lib, _grid(tau_tilde=0.5))[0] == -4           # BGK stability
     assert _create(lib, _grid(dt=0.1))[0] == -4                  # 2D Courant
