@@ -15,7 +15,7 @@ import math
 
 import numpy as np
 
-from . import _lib
+from . import _lib, trace
 from .sim import LbwError, Sim
 
 
@@ -87,9 +87,10 @@ def loss_and_grad(cfg, weights, every=100, grad_out=1.0, timing=False):
 
     ckpt = {}
     mark("fwd0")
-    for n0 in range(0, steps, every):
-        ckpt[n0] = sim.save_state_device()
-        sim.step(min(every, steps - n0))
+    with trace.marker("adjoint forward"):
+        for n0 in range(0, steps, every):
+            ckpt[n0] = sim.save_state_device()
+            sim.step(min(every, steps - n0))
     mark("fwd1")
     loss = r.loss()
 
@@ -113,15 +114,17 @@ def loss_and_grad(cfg, weights, every=100, grad_out=1.0, timing=False):
     for n0 in sorted(ckpt, reverse=True):
         n1 = min(n0 + every, steps)
         mark("rec0")
-        sim.load_state_device(ckpt[n0], n0)
-        sim.save_state_device(buf[0:sb])
-        sim.step_record(n1 - n0, buf[sb:], sb)
+        with trace.marker("adjoint recompute"):
+            sim.load_state_device(ckpt[n0], n0)
+            sim.save_state_device(buf[0:sb])
+            sim.step_record(n1 - n0, buf[sb:], sb)
         mark("rec1")
         mark("adj0")
-        for n in range(n1 - 1, n0 - 1, -1):
-            m = n - n0
-            check(lib.lbw_adjoint_step(h, vp(buf[m * sb:].data_ptr()), vp(buf[(m + 1) * sb:].data_ptr()), n,
-                                       vp(adj.data_ptr()), vp(grad.data_ptr()), vp(scratch.data_ptr())))
+        with trace.marker("adjoint reverse"):
+            for n in range(n1 - 1, n0 - 1, -1):
+                m = n - n0
+                check(lib.lbw_adjoint_step(h, vp(buf[m * sb:].data_ptr()), vp(buf[(m + 1) * sb:].data_ptr()), n,
+                                           vp(adj.data_ptr()), vp(grad.data_ptr()), vp(scratch.data_ptr())))
         mark("adj1")
     check(lib.lbw_adjoint_init_fields(h, vp(adj.data_ptr()), vp(grad.data_ptr()), vp(scratch.data_ptr())))
     torch.cuda.synchronize(dev)

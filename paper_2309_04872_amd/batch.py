@@ -7,7 +7,7 @@ import ctypes
 
 import numpy as np
 
-from . import _lib
+from . import _lib, trace
 from .sim import LbwError
 
 
@@ -77,7 +77,8 @@ class Batch:
         return self
 
     def step(self, nsteps=1, graph=False):
-        self._check(self._lib.lbw_batch_step(self._h, int(nsteps), int(bool(graph))))
+        with trace.marker("lbw_batch_step"):
+            self._check(self._lib.lbw_batch_step(self._h, int(nsteps), int(bool(graph))))
         return self
 
     @property

@@ -6,7 +6,7 @@ import ctypes
 
 import numpy as np
 
-from . import _lib
+from . import _lib, trace
 
 
 class LbwError(RuntimeError):
@@ -118,7 +118,8 @@ class Sim:
         return self
 
     def step(self, nsteps=1):
-        self._check(self._lib.lbw_step(self._h, int(nsteps)))
+        with trace.marker("lbw_step"):
+            self._check(self._lib.lbw_step(self._h, int(nsteps)))
         return self
 
     @property
