@@ -150,7 +150,8 @@ lbw_status lbw_init_plasma(lbw_sim *sim, const lbw_plasma_desc *plasma);
 
 /* Equilibrium populations of arbitrary advected scalars A[K][nx][nz]
  * (K = 2/4 in 1D, 3/8 in 2D for LEC/WARMC, in the order of the paper's
- * advected vectors) moving at u; fields zero; mu as given. */
+ * advected vectors) moving at u; fields zero; mu as given (>= 0, else
+ * LBW_ERR_ARG). */
 lbw_status lbw_init_moments(lbw_sim *sim, double mu, const double *A,
                             const double *uz, const double *ux);
 
@@ -158,7 +159,9 @@ lbw_status lbw_init_moments(lbw_sim *sim, double mu, const double *A,
  * E, B to the field of the bunch alone at t = 0 (Sec. 5): 1D the causal
  * Gauss-consistent E_z, 2D the vacuum solution travelling at c (in the
  * axisymmetric geometry from the cylindrical Gauss law; there the bunch sits
- * on the axis, x0 = 0, else LBW_ERR_ARG). */
+ * on the axis, x0 = 0, else LBW_ERR_ARG). Setting the fields needs a
+ * canonical state (LBW_ERR_STATE otherwise); a rejected call changes
+ * nothing. */
 lbw_status lbw_init_driver(lbw_sim *sim, const lbw_driver_desc *driver,
                            int init_fields);
 

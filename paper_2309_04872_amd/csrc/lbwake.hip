@@ -626,6 +626,7 @@ lbw_status lbw_init_plasma(lbw_sim *s, const lbw_plasma_desc *p)
 lbw_status lbw_init_moments(lbw_sim *s, double mu, const double *Ah, const double *uzh, const double *uxh)
 {
     if (!s || !Ah) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!(mu >= 0.0)) return fail(s, LBW_ERR_ARG, "mu must be >= 0");
     lbw_status st = reset_common(s, mu);
     if (st != LBW_OK) return st;
     const size_t nc = (size_t)s->g.nz * s->g.nx;
@@ -646,6 +647,8 @@ lbw_status lbw_init_driver(lbw_sim *s, const lbw_driver_desc *d, int init_fields
     if (d->nslices < 0 || d->nslices > MAX_SLICES || (d->nslices > 0 && !d->slice_w) ||
         (d->nslices > 0 && !(d->slice_zmax > d->slice_zmin)))
         return fail(s, LBW_ERR_ARG, "invalid slice description");
+    const bool set_fields = init_fields && d->alpha != 0.0;
+    if (set_fields && !s->canonical) return fail(s, LBW_ERR_STATE, "fields can only be set on a canonical state");
     Driver v{};
     v.alpha = d->alpha;
     v.sigma_z = d->sigma_z;
@@ -662,8 +665,7 @@ lbw_status lbw_init_driver(lbw_sim *s, const lbw_driver_desc *d, int init_fields
         HIPCHK(s, hipMemcpyAsync(s->ws + s->L.slice, d->slice_w, d->nslices * sizeof(double),
                                  hipMemcpyHostToDevice, s->stream));
     s->drv = v;
-    if (init_fields && d->alpha != 0.0) {
-        if (!s->canonical) return fail(s, LBW_ERR_STATE, "fields can only be set on a canonical state");
+    if (set_fields) {
         StepArgs a = base_args(s);
         const int nb = (a.ncell + 255) / 256;
         double *ez = (double *)(s->ws + s->L.fld[s->fcur][0]);

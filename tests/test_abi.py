@@ -107,6 +107,12 @@ def test_create_validation(lib):
     assert b"init" in lib.lbw_last_error(h)
     assert lib.lbw_step_record(h, 1, ctypes.c_void_p(512 * 1024), 1 << 20) == -6
     assert lib.lbw_step_record(None, 1, ctypes.c_void_p(512 * 1024), 1 << 20) == -1
+    # argument checks that come before any device work
+    A = (ctypes.c_double * 3)()
+    assert lib.lbw_init_moments(h, -1e-3, A, None, None) == -1   # mu < 0
+    assert b"mu" in lib.lbw_last_error(h)
+    drv = _lib.DriverDesc(alpha=0.5, sigma_z=0.5, sigma_x=0.5)
+    assert lib.lbw_init_driver(h, ctypes.byref(drv), 1) == -6     # before init
     lib.lbw_destroy(h)
     assert _create(lib, _grid(tau_tilde=0.5))[0] == -4           # BGK stability
     assert _create(lib, _grid(dt=0.1))[0] == -4                  # 2D Courant
