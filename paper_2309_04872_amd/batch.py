@@ -40,10 +40,13 @@ class Batch:
         if nbytes == 0:
             raise LbwError(-1, "invalid instance descriptor")
         self.device = torch.device(device)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
+        # allocated on the batch's stream, so that a freed workspace is reused
+        # only after the work queued there
+        with torch.cuda.stream(stream):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
         rc = self._lib.lbw_batch_create(arr, self.n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                                         ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))

@@ -56,10 +56,14 @@ class Sim:
             rc = self._lib.lbw_create(ctypes.byref(self.grid), None, 0, None, ctypes.byref(h))
             raise LbwError(rc if rc != 0 else -1, "invalid or unsupported grid descriptor")
         self.device = torch.device(device)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
+        # allocated on the simulation's stream: once freed, the caching
+        # allocator reuses the block only in that stream's order, after the
+        # work queued there
+        with torch.cuda.stream(stream):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
         rc = self._lib.lbw_create(ctypes.byref(self.grid), ctypes.c_void_p(self.workspace.data_ptr()),
                                   nbytes, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
@@ -132,9 +136,12 @@ class Sim:
         return out if self.dims == 2 else out[0]
 
     def read_device(self, which):
+        """The observable as a device tensor, written on the simulation's
+        stream (work on another stream must wait for it)."""
         import torch
 
-        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         self._check(self._lib.lbw_read_moment_device(self._h, _lib.MOMENTS[which],
                                                      ctypes.c_void_p(out.data_ptr())))
         return out
@@ -171,7 +178,8 @@ class Sim:
 
         n = self.state_device_bytes()
         if out is None:
-            out = torch.empty(n, dtype=torch.uint8, device=self.device)
+            with torch.cuda.stream(self.stream):
+                out = torch.empty(n, dtype=torch.uint8, device=self.device)
         self._check(self._lib.lbw_save_state_device(self._h, ctypes.c_void_p(out.data_ptr())))
         return out
 
