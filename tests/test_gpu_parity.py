@@ -21,7 +21,8 @@ def _quantities(closure, dims):
 
 
 # ---------------------------------------------------------------------------
-# Small grids spanning several tiles with ragged tails (1D tile 256, 2D 32 x 8)
+# Small grids spanning several tiles with ragged tails (1D tiles of 192 or 256
+# nodes, 2D tiles from 64 x 16 down to 32 x 8 nodes)
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 @pytest.mark.parametrize("closure", ["lec", "warmc"])
@@ -39,7 +40,7 @@ def test_parity_1d_driven(closure, storage):
 
 @pytest.mark.parametrize("closure", ["lec", "warmc"])
 def test_parity_1d_long_grid(closure):
-    """9000 nodes: the persistent 1D kernel runs 1024-node tiles (512 below
+    """9000 nodes: the persistent 1D kernel runs 256-node tiles (192 up to
     8192 nodes); ragged last tile."""
     nz = 9000
     n = workloads.density_noise((1, nz), 1e-3, 17)[0]
@@ -60,6 +61,25 @@ def test_parity_2d_driven(closure, storage):
     s.step(60)
     o.step(60)
     compare(s, o, _quantities(closure, 2), TOL[storage])
+
+
+@pytest.mark.parametrize("dims", [1, 2])
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_parity_cold_limit(closure, dims):
+    """mu = 0, the cold plasma: the local-equilibrium recovery reduces to
+    p = |A_1| / n and the warm closure carries no pressure (lambda = gamma);
+    driven, ragged sizes, 1D long enough for the multi-step passes."""
+    if dims == 1:
+        nz, nx, d, steps = 700, 1, 2 * np.pi / 128, 90
+        drv = dict(alpha=0.5, sigma_z=0.5, z0=3.0)
+    else:
+        nz, nx, d, steps = 150, 36, 2 * np.pi / 32, 50
+        drv = dict(alpha=0.8, sigma_z=1.0, sigma_x=0.5, z0=4.0)
+    n = workloads.density_noise((nx, nz), 1e-3, 23)
+    s, o = make_pair(dims, nz, nx, delta=d, closure=closure, mu=0.0, n=n[0] if dims == 1 else n, driver=drv)
+    s.step(steps)
+    o.step(steps)
+    compare(s, o, _quantities(closure, dims), TOL["fp64"])
 
 
 @pytest.mark.parametrize("closure", ["lec", "warmc"])
