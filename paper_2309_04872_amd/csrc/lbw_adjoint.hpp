@@ -382,7 +382,8 @@ __device__ __forceinline__ int slice_of(const Driver &d, double zeta)
 // ((i + 1/2) delta, x_j, t^{n+1/2}), n_b = alpha w_s exp(-e). One workgroup per
 // column of the bunch window [i0, i0 + gridDim.x) sums over x (tree
 // reduction, fixed order) into col[i], with the column's slice in
-// col[nz + i]; then one thread per slice adds its columns in order.
+// col[nz + i]; then the first thread of each slice's run of columns adds
+// them in order.
 __global__ __launch_bounds__(256) void k_adj_drv_cols(AdjArgs a, const double *lez, double t, double zoff, int i0,
                                                       double *col)
 {
@@ -438,31 +439,20 @@ __global__ __launch_bounds__(256) void k_adj_init_cols(AdjArgs a, const double *
 }
 
 // grad[s] += scale * alpha * sum of col[i] over the window's columns of slice
-// s; the window is staged through LDS in chunks of 256 columns.
+// s. zeta grows with the column and slice_of does not decrease with zeta on
+// the slice range (columns outside it hold -1), so the columns of one slice
+// form one run: the thread at a run's first column adds the run in column
+// order, starting from zero, and only it writes grad[s].
 __global__ __launch_bounds__(256) void k_adj_slices(AdjArgs a, const double *col, int i0, int i1, double scale)
 {
-    __shared__ double cv[256];
-    __shared__ int ck[256];
-    const int ns = a.drv.nslices;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // slices threadIdx.x + 256 m, m < 4
-    for (int c0 = i0; c0 < i1; c0 += 256) {
-        const int i = c0 + threadIdx.x;
-        cv[threadIdx.x] = i < i1 ? col[i] : 0.0;
-        ck[threadIdx.x] = i < i1 ? (int)col[a.nz + i] : -1;
-        __syncthreads();
-        const int n = i1 - c0 < 256 ? i1 - c0 : 256;
-        for (int m = 0; m < 4; ++m) {
-            const int s = threadIdx.x + 256 * m;
-            if (s >= ns) break;
-            for (int c = 0; c < n; ++c)
-                if (ck[c] == s) acc[m] += cv[c];
-        }
-        __syncthreads();
-    }
-    for (int m = 0; m < 4; ++m) {
-        const int s = threadIdx.x + 256 * m;
-        if (s < ns) a.grad[s] += scale * a.drv.alpha * acc[m];
-    }
+    const int i = i0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= i1) return;
+    const double *ks = col + a.nz;
+    const int s = (int)ks[i];
+    if (s < 0 || (i > i0 && (int)ks[i - 1] == s)) return;
+    double acc = 0.0;
+    for (int c = i; c < i1 && (int)ks[c] == s; ++c) acc += col[c];
+    a.grad[s] += scale * a.drv.alpha * acc;
 }
 
 }  // namespace lbw

@@ -1114,7 +1114,8 @@ static void adj_step_launch(const AdjArgs &a, double *col, hipStream_t st)
     if (i1 > i0) {
         hipLaunchKernelGGL(k_adj_drv_cols, dim3(i1 - i0), dim3(256), 0, st, a, (const double *)a.lez, th, 0.5, i0,
                            col);
-        hipLaunchKernelGGL(k_adj_slices, dim3(1), dim3(256), 0, st, a, (const double *)col, i0, i1, a.dt);
+        hipLaunchKernelGGL(k_adj_slices, dim3((i1 - i0 + 255) / 256), dim3(256), 0, st, a, (const double *)col, i0, i1,
+                           a.dt);
     }
     hipLaunchKernelGGL(k_adj_stream, dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_adj_collide<ST>), dim3(nb), dim3(256), 0, st, a);
@@ -1161,13 +1162,15 @@ lbw_status lbw_adjoint_init_fields(lbw_sim *s, const double *adj, double *grad, 
     if (i1 > i0) {
         hipLaunchKernelGGL(k_adj_init_cols, dim3(i1 - i0), dim3(256), 0, s->stream, a, (const double *)a.lex, 0.0,
                            0.0, i0, col);
-        hipLaunchKernelGGL(k_adj_slices, dim3(1), dim3(256), 0, s->stream, a, (const double *)col, i0, i1, 1.0);
+        hipLaunchKernelGGL(k_adj_slices, dim3((i1 - i0 + 255) / 256), dim3(256), 0, s->stream, a, (const double *)col, i0,
+                           i1, 1.0);
     }
     slice_window(a, -0.5 * a.dt, 0.5, i0, i1);
     if (i1 > i0) {
         hipLaunchKernelGGL(k_adj_init_cols, dim3(i1 - i0), dim3(256), 0, s->stream, a, (const double *)a.lby,
                            -0.5 * a.dt, 0.5, i0, col);
-        hipLaunchKernelGGL(k_adj_slices, dim3(1), dim3(256), 0, s->stream, a, (const double *)col, i0, i1, 1.0);
+        hipLaunchKernelGGL(k_adj_slices, dim3((i1 - i0 + 255) / 256), dim3(256), 0, s->stream, a, (const double *)col, i0,
+                           i1, 1.0);
     }
     HIPCHK(s, hipGetLastError());
     return LBW_OK;
