@@ -24,9 +24,16 @@ Parity status (the ``-m "not gpu"`` tests under ``tests/test_oracle_*.py``):
   perturbations, e.g. theta^{xz} d_x(lambda u_z));
 - axisymmetric geometry (``tests/test_oracle_axi.py``): pinned by the
   cylindrical Gauss law, the local cold wake, an exact nonlinear breathing
-  column and the column's Langmuir modes; parity unpinned: the nonlinear
-  source -u_r lambda theta^{rz} / r of the warm closure, which no linear or
-  exact solution used there reaches.
+  column, the column's Langmuir modes, and a breathing column carrying a
+  shear temperature theta^{rz} = b(t) r, whose b' = -4 a b at order a b pins
+  the nonlinear source -u_r lambda theta^{rz} / r of the warm closure;
+- diagnostics (``tests/test_oracle_diagnostics.py``): the field and kinetic
+  energies against the conserved energy of uniform cold oscillations and the
+  closed-form energy of the bunch's initial field, the axisymmetric volume
+  weights against exact column sums, max |u| / Lambda against the imposed
+  flow.
+The diagnostics pins and the theta^{rz} pin are shown to fail for planted
+mistakes compiled by ``variant()``.
 """
 from __future__ import annotations
 
@@ -85,45 +92,73 @@ class _Params(ctypes.Structure):
 _lib = None
 
 
+def _configure(L):
+    """Argument and result types of the oracle's C entry points."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_create.restype = ctypes.c_void_p
+    L.orc_create.argtypes = [ctypes.POINTER(_Params)]
+    L.orc_destroy.argtypes = [ctypes.c_void_p]
+    L.orc_init.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int]
+    L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.orc_step_count.restype = ctypes.c_long
+    L.orc_step_count.argtypes = [ctypes.c_void_p]
+    L.orc_get.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+    L.orc_diagnostics.argtypes = [ctypes.c_void_p, dp]
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_num_threads.restype = ctypes.c_int
+    L.orc_feq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_double, ctypes.c_double, dp]
+    L.orc_lec_recover.restype = ctypes.c_int
+    L.orc_lec_recover.argtypes = [ctypes.c_double] * 5 + [dp]
+    L.orc_warmc_recover.argtypes = [ctypes.c_int, dp, dp]
+    L.orc_ppar.restype = ctypes.c_double
+    L.orc_ppar.argtypes = [ctypes.c_double] * 6
+    L.orc_lambda0.restype = ctypes.c_double
+    L.orc_lambda0.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.orc_init_moments.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    L.orc_set_yee.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+    L.orc_num_scalars.restype = ctypes.c_int
+    L.orc_num_scalars.argtypes = [ctypes.c_void_p]
+    L.orc_ade_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                              ctypes.c_double, ctypes.c_double, dp, ctypes.c_int, dp]
+    L.orc_bunch.restype = ctypes.c_double
+    L.orc_bunch.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_SO)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.orc_create.restype = ctypes.c_void_p
-        L.orc_create.argtypes = [ctypes.POINTER(_Params)]
-        L.orc_destroy.argtypes = [ctypes.c_void_p]
-        L.orc_init.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.c_int]
-        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        L.orc_step_count.restype = ctypes.c_long
-        L.orc_step_count.argtypes = [ctypes.c_void_p]
-        L.orc_get.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
-        L.orc_diagnostics.argtypes = [ctypes.c_void_p, dp]
-        L.orc_set_threads.argtypes = [ctypes.c_int]
-        L.orc_num_threads.restype = ctypes.c_int
-        L.orc_feq.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                              ctypes.c_double, ctypes.c_double, dp]
-        L.orc_lec_recover.restype = ctypes.c_int
-        L.orc_lec_recover.argtypes = [ctypes.c_double] * 5 + [dp]
-        L.orc_warmc_recover.argtypes = [ctypes.c_int, dp, dp]
-        L.orc_ppar.restype = ctypes.c_double
-        L.orc_ppar.argtypes = [ctypes.c_double] * 6
-        L.orc_lambda0.restype = ctypes.c_double
-        L.orc_lambda0.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.orc_init_moments.argtypes = [ctypes.c_void_p, dp, dp, dp]
-        L.orc_set_yee.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
-        L.orc_num_scalars.restype = ctypes.c_int
-        L.orc_num_scalars.argtypes = [ctypes.c_void_p]
-        L.orc_ade_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                  ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                  ctypes.c_double, ctypes.c_double, dp, ctypes.c_int, dp]
-        L.orc_bunch.restype = ctypes.c_double
-        L.orc_bunch.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_double]
-        _lib = L
+        _lib = _configure(ctypes.CDLL(_SO))
     return _lib
+
+
+def variant(tag, replacements):
+    """A copy of the oracle with planted mistakes, for tests showing that a
+    pin fails when the arithmetic it covers is wrong. ``replacements`` is a
+    list of (old, new) source strings; each ``old`` must occur exactly once in
+    ``lbw_oracle.c``. The copy is compiled with the same flags into a
+    temporary directory and returned as a loaded library, to be passed to
+    ``Oracle(..., library=...)``."""
+    import tempfile
+
+    src = open(_SRC).read()
+    for old, new in replacements:
+        if src.count(old) != 1:
+            raise ValueError(f"planted mistake {tag!r}: {old!r} occurs {src.count(old)} times")
+        src = src.replace(old, new)
+    d = os.path.join(tempfile.gettempdir(), f"lbw_oracle_variant_{os.getpid()}")
+    os.makedirs(d, exist_ok=True)
+    c, so = os.path.join(d, f"{tag}.c"), os.path.join(d, f"lib{tag}.so")
+    with open(c, "w") as fh:
+        fh.write(src)
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    "-I", _HERE, "-w", c, "-o", so, "-lm"], check=True)
+    return _configure(ctypes.CDLL(so))
 
 
 def _dp(a):
@@ -140,12 +175,13 @@ def num_threads() -> int:
 
 class Oracle:
     """One simulation on the CPU oracle. Keyword arguments mirror the C
-    ``orc_params`` fields; arrays are [nx][nz] with z fastest."""
+    ``orc_params`` fields; arrays are [nx][nz] with z fastest. ``library``: a
+    planted-mistake copy from ``variant()`` (default: the oracle itself)."""
 
     def __init__(self, dims, nz, nx=1, delta=2 * np.pi / 128, dt=None, tau_tilde=None,
                  closure=LEC, dvel=None, bc_z=OPEN, bc_x=OPEN, mu=1e-3, alpha=0.0,
                  sigma_z=1.0, sigma_x=1.0, z0=None, x0=0.0, slice_w=None,
-                 slice_zmin=0.0, slice_zmax=0.0, geom=0):
+                 slice_zmin=0.0, slice_zmax=0.0, geom=0, library=None):
         if dt is None:
             dt = 0.1 * delta
         if tau_tilde is None:
@@ -154,6 +190,7 @@ class Oracle:
             dvel = 1.0 if dims == 1 else 3.0
         if z0 is None:
             z0 = 6.0 * sigma_z
+        self._L = library if library is not None else lib()
         self._keep = None
         p = _Params(dims, nz, nx, delta, dt, tau_tilde, closure, float(dvel), bc_z, bc_x,
                     mu, alpha, sigma_z, sigma_x, z0, x0, 0, slice_zmin, slice_zmax, None, int(geom))
@@ -165,15 +202,15 @@ class Oracle:
         self.params = p
         self.dims, self.nz, self.nx = dims, nz, nx
         self.shape = (nx, nz)
-        h = lib().orc_create(ctypes.byref(p))
+        h = self._L.orc_create(ctypes.byref(p))
         if not h:
             raise ValueError("oracle rejected the parameters")
         self._h = ctypes.c_void_p(h)
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
-            _lib.orc_destroy(h)
+        if h is not None and getattr(self, "_L", None) is not None:
+            self._L.orc_destroy(h)
             self._h = None
 
     def _arr(self, a):
@@ -185,52 +222,52 @@ class Oracle:
     def init(self, n=None, uz=None, ux=None, fields_from_driver=True):
         n, uz, ux = self._arr(n), self._arr(uz), self._arr(ux)
         self._init_keep = (n, uz, ux)
-        lib().orc_init(self._h, _dp(n) if n is not None else None,
-                       _dp(uz) if uz is not None else None,
-                       _dp(ux) if ux is not None else None, int(bool(fields_from_driver)))
+        self._L.orc_init(self._h, _dp(n) if n is not None else None,
+                         _dp(uz) if uz is not None else None,
+                         _dp(ux) if ux is not None else None, int(bool(fields_from_driver)))
         return self
 
     @property
     def nscalars(self):
-        return int(lib().orc_num_scalars(self._h))
+        return int(self._L.orc_num_scalars(self._h))
 
     def init_moments(self, A, uz=None, ux=None):
         """Equilibrium populations of arbitrary scalars A[K][nx][nz] (1D: A[K][nz])."""
         A = np.ascontiguousarray(np.asarray(A, dtype=np.float64).reshape(self.nscalars, *self.shape))
         uz, ux = self._arr(uz), self._arr(ux)
         self._init_keep = (A, uz, ux)
-        lib().orc_init_moments(self._h, _dp(A), _dp(uz) if uz is not None else None,
-                               _dp(ux) if ux is not None else None)
+        self._L.orc_init_moments(self._h, _dp(A), _dp(uz) if uz is not None else None,
+                                 _dp(ux) if ux is not None else None)
         return self
 
     def set_yee(self, which, v):
         """Overwrite a raw Yee array: 'ez', 'ex' (E^n) or 'by' (B^{n-1/2})."""
         v = self._arr(v)
-        lib().orc_set_yee(self._h, {"ez": 0, "ex": 1, "by": 2}[which], _dp(v))
+        self._L.orc_set_yee(self._h, {"ez": 0, "ex": 1, "by": 2}[which], _dp(v))
         return self
 
     def step(self, nsteps=1):
-        lib().orc_step(self._h, int(nsteps))
+        self._L.orc_step(self._h, int(nsteps))
         return self
 
     @property
     def step_count(self):
-        return int(lib().orc_step_count(self._h))
+        return int(self._L.orc_step_count(self._h))
 
     def get(self, which):
         out = np.empty(self.shape, dtype=np.float64)
-        rc = lib().orc_get(self._h, OBS[which], _dp(out))
+        rc = self._L.orc_get(self._h, OBS[which], _dp(out))
         if rc != 0:
             raise ValueError(which)
         return out if self.dims == 2 else out[0]
 
     def diagnostics(self):
         out = np.zeros(8)
-        lib().orc_diagnostics(self._h, _dp(out))
+        self._L.orc_diagnostics(self._h, _dp(out))
         return out
 
     def bunch(self, z, x, t):
-        return lib().orc_bunch(self._h, z, x, t)
+        return self._L.orc_bunch(self._h, z, x, t)
 
 
 def feq(dims, A, uz, ux, lattice_speed):
