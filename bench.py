@@ -1,19 +1,25 @@
 """Benchmark of the fused LB + field step on one MI355X.
 
-Workload (default): the 2D local-equilibrium wake, 2048 x 512 nodes,
-delta = lambda_p/64, FP32 populations with FP64 closure recovery, mu = 1e-2,
-bi-Gaussian driver (sigma_z = 1, sigma_x = 0.5, n_b/n0 = 1), 8000 steps. One
-"step" is one pass of the whole hot path over the grid: streaming, moments,
-recovery, forcing, collision and the Yee field update, i.e. one fused kernel
-launch. Inputs are synthetic (uniform plasma, analytic bunch) and resident in
-HBM before the timed region.
+Workload (default): the 2D warm-closure wake, 4096 x 1024 nodes,
+delta = lambda_p/64, FP64 populations, mu = 5e-2, bi-Gaussian driver
+(sigma_z = 1, sigma_x = 0.5, n_b/n0 = 2): the largest configuration, at the
+paper's presumed precision. One "step" is one pass of the whole hot path over
+the grid: streaming, moments, recovery, forcing, collision and the Yee field
+update, i.e. one fused kernel launch. Inputs are synthetic (uniform plasma,
+analytic bunch) and resident in HBM before the timed region. Without --steps
+it runs 400 steps: the warm closure's temperature theta^zz first turns
+negative near t = 4.5 (step ~459) in this strongly driven case, in the oracle
+as in the kernels.
 
 Prints one JSON line: MLUPS of the whole job, the HBM roofline of the fused
 kernel (algorithmic bytes per lattice update over its HIP-event-measured
-average duration) and the CPU oracle timed on the host's cores.
+average duration), the CPU oracle timed on the host's cores, and for the
+default workload the FP32 and FP16-deviation storage variants: their fused
+kernel time and the relative L2 error of density perturbation, momentum and
+E_z against the FP64 run after 400 steps.
 
-Other workloads (--workload): wake1d_lec_fp64, wake2d_warmc (--storage fp64 |
-fp32 | fp16dev), batch1d_scan, wake2d_lec_adjoint, and wake_axi_lec /
+Other workloads (--workload): wake2d_lec_fp32, wake1d_lec_fp64, wake2d_warmc
+(--storage fp64 | fp32 | fp16dev), batch1d_scan, wake2d_lec_adjoint, and wake_axi_lec /
 wake_axi_warmc, the paper's own axisymmetric production case (3000 x 600
 nodes, 30 000 steps, FP64), the one workload for which the paper states a
 throughput: there vs_baseline is the ratio to it (a 96-core CPU cluster;
@@ -48,8 +54,11 @@ def bytes_per_lu(dims, closure, storage):
 
 # HBM-side bytes per launch of the fused kernel, measured with rocprofv3
 # --pmc FETCH_SIZE and WRITE_SIZE and scaled by a 1 GiB copy
-# (the summaries and commands are in profiles/k_step2d_*.md). Valid for the
-# kernel as profiled; remove an entry when the kernel changes.
+# (the summaries and commands are in profiles/k_step2d_*.md). FETCH_SIZE
+# counts the L2's requests to memory, and the 256 MB last-level cache (MALL)
+# sits behind that point: for grids whose state exceeds it (wake2d_warmc,
+# 5.4 GB in FP64) the bytes are HBM bytes up to the re-reads that hit the
+# MALL. Valid for the kernel as profiled; remove an entry when it changes.
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake2d_lec_fp32", "fp32"): 301.1e6,
     ("wake2d_lec_fp32", "fp64"): 605.2e6,
@@ -198,6 +207,52 @@ def fd_fp64_gpu(cfg, weights):
             "kind": "central differences of FP64 forward runs on the GPU (one run timed, x 128)"}
 
 
+# Steps a workload runs when --steps is not given, where its full length
+# leaves the closure's range of validity: the strongly driven warm wake's
+# temperature theta^zz first turns negative near t = 4.5 (step ~459), in the
+# oracle as in the kernels, independently of dt and delta.
+VALID_WINDOW_STEPS = {"wake2d_warmc": 400}
+
+
+def precision_variants(w, steps=400):
+    """The same workload with FP64, FP32 and FP16-deviation population
+    storage: each run for ``steps`` steps from t = 0 (fused kernel timed with
+    HIP events on the simulation's stream), then the relative L2 error of the
+    density perturbation n - 1, the momentum densities n gamma u_z,
+    n gamma u_x and the node E_z against the FP64 run."""
+    import torch
+
+    from paper_2309_04872_amd.sim import Sim
+
+    cells = w["nz"] * w["nx"]
+    out, ref = {}, None
+    for storage in ("fp64", "fp32", "fp16dev"):
+        s = Sim(w["dims"], w["nz"], w["nx"], delta=w["delta"], dt=w["dt"], tau_tilde=w["tau_tilde"],
+                closure=w["closure"], dvel=w["dvel"], storage=storage, geom=w["geom"])
+        s.init_plasma(w["mu"])
+        s.init_driver(w["alpha"], w["sigma_z"], w["sigma_x"], z0=w["z0"])
+        s.set_timing(True)
+        s.step(steps)
+        k_ms, k_n = s.get_timing()
+        s.set_timing(False)
+        got = {"n-1": s.read("n") - 1.0, "mz": s.read("mz"), "mx": s.read("mx"), "ez": s.field("ez")}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        k_s = k_ms / k_n / 1e3
+        blu = bytes_per_lu(w["dims"], w["closure"], storage)
+        rec = {"kernel_avg_us": k_s * 1e6, "mlups_kernel": cells / k_s / 1e6, "bytes_per_lu": blu,
+               "frac": blu * cells / k_s / 1e9 / HBM_PEAK_GBS, "steps": steps}
+        if ref is None:
+            ref = got
+        else:
+            rec["rel_l2_vs_fp64"] = {q: float(np.linalg.norm(got[q] - ref[q]) / np.linalg.norm(ref[q]))
+                                     for q in got}
+            rec["speedup_vs_fp64"] = out["fp64"]["kernel_avg_us"] / rec["kernel_avg_us"]
+        out[storage] = rec
+    return out
+
+
 def batch_bytes_per_step(insts):
     """Algorithmic bytes of one step of the batched scan: per instance
     bytes_per_lu(1, closure, FP64) times its node count."""
@@ -205,6 +260,18 @@ def batch_bytes_per_step(insts):
 
 
 BATCH_TRAFFIC_PER_STEP = 33.55e6
+BATCH_PASS_DEPTH = 16
+
+
+def batch_sweeps(steps, depth=BATCH_PASS_DEPTH):
+    """Sweeps of the whole state in one batched launch of ``steps`` steps:
+    the first step alone, passes of ``depth`` steps, pairs, a last single
+    step, and the closing canonicalisation (the kernel's pass schedule)."""
+    if steps <= 0:
+        return 0
+    rest = steps - 1
+    tail = rest % depth
+    return 1 + rest // depth + tail // 2 + tail % 2 + 1
 
 
 def sequential_fp64(insts, steps):
@@ -308,7 +375,11 @@ def bench_batch(args):
     # calibrated by a 1 GiB copy) for this kernel; the summary is in
     # profiles/k_batch1d_batch1d_scan.md
     traffic_per_step = BATCH_TRAFFIC_PER_STEP
-    achieved = bps * steps / (k_ms / 1e3) / 1e9
+    # the blocked algorithm reads and writes the state once per sweep, not
+    # once per step: its algorithmic bytes per launch are bps x sweeps
+    sweeps = batch_sweeps(steps)
+    achieved = bps * sweeps / (k_ms / 1e3) / 1e9
+    per_step_equiv = bps * steps / (k_ms / 1e3) / 1e9
     line = {
         "metric": "MLUPS (LB+field)",
         "value": cells * steps / (ms_total / 1e3) / 1e6,
@@ -336,24 +407,36 @@ def bench_batch(args):
             "traffic": traffic_per_step * steps if steps == workloads.BATCH_SCAN["steps"] else None,
             "kernel": "k_batch1d",
             "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-            "kernel_avg_us": k_ms * 1e3, "bytes_per_step": bps, "launches": 1,
-            "note": "16 steps per pass reuse the state on chip: HBM moves 0.076x the per-step "
-                    "algorithmic bytes, so frac above 1 means the per-step HBM roofline no longer "
-                    "bounds the kernel (the latency of the longest instance's passes does)",
+            "kernel_avg_us": k_ms * 1e3, "bytes_per_step": bps, "sweeps": sweeps, "launches": 1,
+            "per_step_equivalent_gbs": per_step_equiv,
+            "note": "16 steps per pass: the state is read and written once per sweep, so achieved "
+                    "counts bytes_per_step x sweeps; HBM is far from bounding the launch, which the "
+                    "latency of the longest instance's passes on one compute unit does",
         },
         "wall_s": wall,
         "diagnostics": {"nonfinite_instances": int((bad > 0).sum())},
         "sequential_fp64": sequential_fp64(insts, steps),
     }
+    b.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_batch(insts, args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 
-# Algorithmic bytes per node of one reverse step of the adjoint (FP64 adjoint
-# state, populations of the saved forward states in the storage type): each
-# kernel's reads and writes of full planes, K*Q = 27 population planes.
+# Algorithmic bytes per node of one reverse step of the adjoint: the FP64
+# adjoint of the canonical state (K*Q = 27 population planes and the three
+# Yee arrays) read once and written once, and the two saved forward states
+# (steps n and n + 1: populations in the storage type, three FP64 Yee arrays)
+# read once. 744 B with FP32 populations.
 def adjoint_bytes_per_node(storage):
+    sb = {"fp64": 8, "fp32": 4, "fp16dev": 2}[storage]
+    P = 27
+    return 2 * (P + 3) * 8 + 2 * (P * sb + 3 * 8)
+
+
+# What the implementation's eight reverse-step kernels read and write per node
+# (full planes), for comparison with the algorithmic bytes above.
+def adjoint_impl_bytes_per_node(storage):
     sb = {"fp64": 8, "fp32": 4, "fp16dev": 2}[storage]
     P = 27
     maxwell = 3 * 8 + P * sb + 2 * P * 8 + 8       # adj E, B; f^{n+1}; adj f (+=); adj B'
@@ -410,6 +493,7 @@ def bench_adjoint(args):
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "reverse step (8 kernels)",
             "kernel_avg_us": step_s * 1e6, "bytes_per_node": bpn,
+            "impl_bytes_per_node": adjoint_impl_bytes_per_node(storage),
         },
         "wall_s": wall,
         "phases_ms": tm,
@@ -426,7 +510,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="wake2d_lec_fp32")
+    ap.add_argument("--workload", default="wake2d_warmc")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32 / FP16-dev comparison of the default workload")
     ap.add_argument("--storage", default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -448,7 +534,8 @@ def main():
 
     over = {"storage": args.storage} if args.storage else {}
     w = workloads.workload(args.workload, **over)
-    steps = args.steps if args.steps is not None else w["steps"]
+    default_steps = VALID_WINDOW_STEPS.get(args.workload, w["steps"])
+    steps = args.steps if args.steps is not None else default_steps
     cells = w["nz"] * w["nx"]
 
     def build():
@@ -533,6 +620,10 @@ def main():
             "value": paper, "unit": "MLUPS", "hardware": "96 cores, Intel Xeon E5-2695 @ 2.40 GHz, MPI",
             "source": "Sec. 5: about %d min for 3e4 %s steps on the 3000 x 600 axisymmetric grid"
                       % (PAPER_MINUTES[args.workload], "LEC-LB" if w["closure"] == "lec" else "WARMC-LB")}
+    s.close()
+    del s
+    if args.workload == "wake2d_warmc" and w["storage"] == "fp64" and not args.no_variants:
+        line["precision_variants"] = precision_variants(w)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -168,18 +168,48 @@ lbw_status lbw_init_driver(lbw_sim *sim, const lbw_driver_desc *driver,
 /* Overwrite a raw Yee array (LBW_EZ, LBW_EX: E^n; LBW_BY: B^{n-1/2}). */
 lbw_status lbw_set_field(lbw_sim *sim, int which, const double *host, size_t count);
 
-/* Advance nsteps time steps (asynchronous on the stream). */
+/* Advance nsteps time steps (asynchronous on the stream unless the
+ * non-finite check below is on). One step is the LB time step of Sec. 2.1
+ * (eq. lbe: collision toward the moment-matching equilibrium of Sec. 2.2,
+ * eq. ade-feq, with the source S_i = w_i F of eq. lsource; streaming with
+ * eq. open-bc or periodic wrap) for every advected scalar of the closure
+ * (Sec. 3.1 eq. lb-ade-lec-comps-A/F, Sec. 4.1 eq. lb-ade-warmc-comps-A/F,
+ * App. A), with the forcing from the Lorentz force of the Yee fields and the
+ * gradients of the recovered fluid variables, then the Yee update with the
+ * plasma current -n u and the driver current -n_b z^ (Sec. 5). The call ends
+ * on the canonical state (post-streaming populations f^n, E^n, B^{n-1/2}); a
+ * series of calls equals one call of the summed length bit for bit. */
 lbw_status lbw_step(lbw_sim *sim, int nsteps);
 
+/* Optional non-finite check (0 = off, the default). With every = M > 0,
+ * lbw_step runs in chunks that end on multiples of M steps (counted from
+ * lbw_init_plasma); at the end of each such chunk the kernels that bring the
+ * state to canonical form also test every node's advected scalars, velocity
+ * and fields, and lbw_step returns LBW_ERR_NONFINITE (the state is then the
+ * canonical state of that step, lbw_step_count tells which) as soon as one is
+ * not finite. The check costs no extra pass over the state, but lbw_step
+ * then synchronises the stream after each checked chunk. Results are the
+ * same bits as without the check. The paper's only stability statement is
+ * tau~ > 1/2 (Sec. 2.2, eq. diff-coeff); the check catches the rest. */
+lbw_status lbw_set_nonfinite_check(lbw_sim *sim, int every);
+
 /* Recover one fluid observable at every node into host_out (count =
- * nx*nz doubles); synchronises the stream. */
+ * nx*nz doubles); synchronises the stream. The observables come from the
+ * zeroth moments of the canonical populations (eq. disc-moments-ade) by the
+ * closure's recovery: LEC, the fixed point of Sec. 3.1 for |p| with
+ * n0 = n / gamma and P0 = mu n0^{1+2/D} (eq. temp-scaling); WARMC, the
+ * algebra of Sec. 4.1 and App. A (lambda = n / h, theta^{0i}, theta^{00}
+ * from eq. traces4, P_par by the double boost of eq. double-boost). */
 lbw_status lbw_read_moment(lbw_sim *sim, int which, double *host_out, size_t count);
 
 /* Same into a device buffer of nx*nz doubles, asynchronous on the stream. */
 lbw_status lbw_read_moment_device(lbw_sim *sim, int which, double *device_out);
 
-/* Fields: at_nodes = 1 gives node averages of E^n and B^n; at_nodes = 0 the
- * raw Yee arrays E^n, B^{n-1/2} (ghost slots reported as their copies). */
+/* Fields of the Yee FDTD update (Sec. 5): at_nodes = 1 gives node averages
+ * of E^n and B^n = B^{n-1/2} - dt/2 curl E^n (E over 2, B over 4 slots) and
+ * the transverse wakefield E_x - B_y of the paper's wake plots; at_nodes = 0
+ * the raw Yee arrays E^n, B^{n-1/2} (ghost slots reported as their copies).
+ * count = nx*nz doubles; synchronises the stream. */
 lbw_status lbw_read_field(lbw_sim *sim, int which, int at_nodes, double *host_out,
                           size_t count);
 
@@ -235,7 +265,7 @@ lbw_status lbw_step_record(lbw_sim *sim, int nsteps, void *device_states, size_t
  * Sec. 5): the transposed Jacobian of one step of lbw_step, and the
  * derivatives of the driver's slice weights (per-slice current profile) in
  * the bunch current and in the initial fields. 2D slab, LBW_LEC, any storage
- * (the adjoint itself is FP64), at most 1024 slices; LBW_ERR_UNSUPPORTED
+ * (the adjoint itself is FP64), any slice count lbw_init_driver accepts; LBW_ERR_UNSUPPORTED
  * otherwise, LBW_ERR_STATE when the driver has no slices.
  *
  * adj (device, FP64, caller-owned) holds the adjoint of a canonical state:

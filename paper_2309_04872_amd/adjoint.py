@@ -134,7 +134,9 @@ def loss_and_grad(cfg, weights, every=100, grad_out=1.0, timing=False):
         _TIMING.clear()
         _TIMING.update(forward_ms=total("fwd0", "fwd1"), recompute_ms=total("rec0", "rec1"),
                        adjoint_ms=total("adj0", "adj1"), adjoint_steps=steps)
-    return loss, grad.cpu().numpy()
+    g = grad.cpu().numpy()
+    sim.close()
+    return loss, g
 
 
 def _autograd_function():

@@ -4,6 +4,7 @@ PyTorch provides the device workspace and the stream."""
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 
@@ -59,11 +60,16 @@ class Batch:
             raise LbwError(rc, self._lib.lbw_batch_last_error(self._h).decode())
 
     def close(self):
+        """Release the library handle (its HIP events and graphs). Call it
+        before the interpreter shuts down."""
         if getattr(self, "_h", None):
             self._lib.lbw_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime may already be gone
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

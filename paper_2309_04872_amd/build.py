@@ -10,6 +10,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "lbwake.hip")
 SRCS = [SRC, os.path.join(HERE, "csrc", "lbw_batch.hip")]
 DEPS = [*SRCS, os.path.join(HERE, "csrc", "lbw_kernels.hpp"), os.path.join(HERE, "csrc", "lbw_device.hpp"),
+        os.path.join(HERE, "csrc", "lbw_adjoint.hpp"),
         os.path.join(ROOT, "include", "lbwake.h")]
 SO = os.path.join(HERE, "liblbwake.so")
 ARCH = os.environ.get("LBW_OFFLOAD_ARCH", "gfx950")

@@ -92,6 +92,28 @@ __device__ __forceinline__ int xcd_band_tile(int b, int nblocks)
 }
 
 // ---------------------------------------------------------------------------
+// FP64 reductions across the 64 lanes of a wavefront: butterfly exchanges
+// (__shfl_xor, lane i pairs with lane i ^ o). Both partners of a pair add the
+// same two values, so every lane ends with the same bits and the result does
+// not depend on timing. Lanes outside the data must pass the identity.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// Maximum in which a NaN wins, so that a non-finite value is never hidden.
+__device__ __forceinline__ double wave_max_nan(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, 64);
+        if (w > v || w != w) v = w;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
 // Boundary indexing. Open boundaries copy the nearest bulk node (eq. open-bc);
 // periodic boundaries wrap. Yee arrays along a staggered direction have n - 1
 // real half-integer slots between the n nodes under open boundaries.

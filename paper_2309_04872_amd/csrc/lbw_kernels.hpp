@@ -28,6 +28,7 @@ struct StepArgs {
     double *lag;                 // warm closure lagged values, [NLAG][ncell], in place
     double *lag_alt;             // 1D warm closure: the other lagged-value buffer (multi-step passes)
     unsigned int *fallbacks;     // LEC recovery fallback counter
+    unsigned int *nonfinite;     // set by the finish kernels when a node is not finite (null: no check)
     const double *aref;          // per-scalar storage reference A_ref (device, K values)
     int nz, nx, ncell;
     int bcz, bcx;
@@ -863,12 +864,20 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
         uz = r.uz;
         ux = r.ux;
     }
+    double ezn = 0.0;
     if (DIM == 1) {
         const double jb = driver_density<1>(a.drv, gz * a.delta, 0.0, (a.step - 0.5) * a.dt);
-        a.ez_out[idx] = a.ez_in[idx] + a.dt * (A[0] * uz + jb);
+        ezn = a.ez_in[idx] + a.dt * (A[0] * uz + jb);
+        a.ez_out[idx] = ezn;
     } else {
         jz[idx] = -A[0] * uz;
         jx[idx] = -A[0] * ux;
+    }
+    if (a.nonfinite) {
+        // a non-finite population makes its scalar's sum non-finite
+        double sa = 0.0;
+        for (int k = 0; k < K; ++k) sa += A[k];
+        if (!isfinite(sa) || !isfinite(uz) || !isfinite(ux) || !isfinite(ezn)) atomicOr(a.nonfinite, 1u);
     }
 }
 
@@ -901,12 +910,16 @@ static __global__ void k_finish_e2d(StepArgs a, const double *jz, const double *
     const double th = (a.step - 0.5) * dt;
     const double jxe = 0.5 * (JN(jx, j, i) + JN(jx, j + 1, i));
     const double cx = -(BY(j, i) - BY(j, i - 1)) * id;
-    a.ex_out[idx] = a.ex_in[idx] + dt * (cx - jxe);
+    const double exn = a.ex_in[idx] + dt * (cx - jxe);
+    a.ex_out[idx] = exn;
     const double jze = 0.5 * (JN(jz, j, i) + JN(jz, j, i + 1));
     const double jb = -driver_density<2>(a.drv, (i + 0.5) * a.delta, node_x(j, nx, a.delta, a.axi), th);
     const double cz = a.axi ? ((j + 1.0) * BY(j, i) - (j > 0 ? j * BY(j - 1, i) : 0.0)) / ((j + 0.5) * a.delta)
                             : (BY(j, i) - BY(j - 1, i)) * id;
-    a.ez_out[idx] = a.ez_in[idx] + dt * (cz - jze - jb);
+    const double ezn = a.ez_in[idx] + dt * (cz - jze - jb);
+    a.ez_out[idx] = ezn;
+    if (a.nonfinite && !(isfinite(ezn) && isfinite(exn) && isfinite(a.by_out[idx])))
+        atomicOr(a.nonfinite, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -1036,18 +1049,46 @@ __global__ void k_read_field(StepArgs a, int which, int at_nodes, double *out)
 }
 
 // ---------------------------------------------------------------------------
-// Diagnostics: per-block FP64 partial sums (sum n, field energy, kinetic
-// energy, Gauss residual^2, non-finite count) and maxima (|u| / Lambda),
-// combined in a fixed order by a single block.
+// Diagnostics: per-node FP64 terms (n dV, field energy, kinetic energy,
+// Gauss residual^2, non-finite flag, |u| / Lambda) reduced across each
+// wavefront with butterfly exchanges, then across the workgroup's waves in
+// wave order, then over the workgroups by one final workgroup (each lane
+// takes a fixed strided set of partials in order). Sums for the first five,
+// a maximum in which NaN wins for the last. The order is fixed, so the
+// result is bitwise reproducible.
 constexpr int NDIAG = 6;
+constexpr int DIAG_THREADS = 256;
+
+// Reduce v[NDIAG] over the workgroup; thread 0 gets the result.
+__device__ __forceinline__ void block_reduce_diag(double *v, double (*red)[DIAG_THREADS / 64])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 0; d < NDIAG - 1; ++d) v[d] = wave_sum(v[d]);
+    v[NDIAG - 1] = wave_max_nan(v[NDIAG - 1]);
+    if (lane == 0)
+#pragma unroll
+        for (int d = 0; d < NDIAG; ++d) red[d][wave] = v[d];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < NDIAG; ++d) v[d] = red[d][0];
+        for (int w = 1; w < DIAG_THREADS / 64; ++w) {
+#pragma unroll
+            for (int d = 0; d < NDIAG - 1; ++d) v[d] += red[d][w];
+            const double o = red[NDIAG - 1][w];
+            if (o > v[NDIAG - 1] || o != o) v[NDIAG - 1] = o;
+        }
+    }
+}
 
 template <int DIM, int CL, class ST>
-__global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, double *part)
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag_partial(StepArgs a, double *part)
 {
     using L = Lattice<DIM>;
     constexpr int Q = L::Q;
     constexpr int K = NScal<DIM, CL>::K;
-    __shared__ double red[NDIAG][256];
+    __shared__ double red[NDIAG][DIAG_THREADS / 64];
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     double v[NDIAG] = {0, 0, 0, 0, 0, 0};
     if (idx < a.ncell) {
@@ -1089,6 +1130,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, double *part)
             fe = 0.5 * e * e * dV;
             div = (a.ez_in[fix_node(i + 1, nz, bz)] - a.ez_in[fix_node(i - 1, nz, bz)]) * (0.5 / a.delta);
         } else {
+            // energy of the real Yee slots only
             const bool rz = bz == BC_PERIODIC || i < nz - 1, rx = bx == BC_PERIODIC || j < nx - 1;
             const double ez = a.ez_in[idx], ex = a.ex_in[idx], by = a.by_in[idx];
             if (axi)
@@ -1113,41 +1155,23 @@ __global__ __launch_bounds__(256) void k_diag_partial(StepArgs a, double *part)
         v[4] = bad ? 1.0 : 0.0;
         v[5] = sqrt(uu) / a.lam;
     }
-    for (int d = 0; d < NDIAG; ++d) red[d][threadIdx.x] = v[d];
-    __syncthreads();
-    for (int sft = 128; sft > 0; sft >>= 1) {
-        if ((int)threadIdx.x < sft) {
-            for (int d = 0; d < 5; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + sft];
-            const double o = red[5][threadIdx.x + sft];
-            if (o > red[5][threadIdx.x] || o != o) red[5][threadIdx.x] = o;
-        }
-        __syncthreads();
-    }
+    block_reduce_diag(v, red);
     if (threadIdx.x == 0)
-        for (int d = 0; d < NDIAG; ++d) part[(size_t)d * gridDim.x + blockIdx.x] = red[d][0];
+        for (int d = 0; d < NDIAG; ++d) part[(size_t)d * gridDim.x + blockIdx.x] = v[d];
 }
 
-static __global__ __launch_bounds__(256) void k_diag_final(const double *part, int nblocks, double *out)
+static __global__ __launch_bounds__(DIAG_THREADS) void k_diag_final(const double *part, int nblocks, double *out)
 {
-    __shared__ double red[NDIAG][256];
+    __shared__ double red[NDIAG][DIAG_THREADS / 64];
     double v[NDIAG] = {0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += 256) {
-        for (int d = 0; d < 5; ++d) v[d] += part[(size_t)d * nblocks + b];
-        const double o = part[(size_t)5 * nblocks + b];
-        if (o > v[5] || o != o) v[5] = o;
+    for (int b = threadIdx.x; b < nblocks; b += DIAG_THREADS) {
+        for (int d = 0; d < NDIAG - 1; ++d) v[d] += part[(size_t)d * nblocks + b];
+        const double o = part[(size_t)(NDIAG - 1) * nblocks + b];
+        if (o > v[NDIAG - 1] || o != o) v[NDIAG - 1] = o;
     }
-    for (int d = 0; d < NDIAG; ++d) red[d][threadIdx.x] = v[d];
-    __syncthreads();
-    for (int sft = 128; sft > 0; sft >>= 1) {
-        if ((int)threadIdx.x < sft) {
-            for (int d = 0; d < 5; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + sft];
-            const double o = red[5][threadIdx.x + sft];
-            if (o > red[5][threadIdx.x] || o != o) red[5][threadIdx.x] = o;
-        }
-        __syncthreads();
-    }
+    block_reduce_diag(v, red);
     if (threadIdx.x == 0)
-        for (int d = 0; d < NDIAG; ++d) out[d] = red[d][0];
+        for (int d = 0; d < NDIAG; ++d) out[d] = v[d];
 }
 
 // Analytic field of the bunch alone at t = 0 (Sec. 5). 1D: E_z(z) = alpha

@@ -3,6 +3,7 @@ the device workspace and the stream; the binding only marshals arguments."""
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 
@@ -82,15 +83,36 @@ class Sim:
         return np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), self.shape))
 
     def close(self):
+        """Release the library handle (and its HIP events). Call it before the
+        interpreter shuts down; the workspace tensor stays torch's."""
         if getattr(self, "_h", None):
             self._lib.lbw_destroy(self._h)
             self._h = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime (or a profiler's hooks
+        # around it) may already be gone: leave the handle to the process exit
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+
+    def _device_buffer(self, buf, nbytes, what):
+        """Refuse a buffer the C side could not use safely: it reads or writes
+        nbytes at buf.data_ptr() on this simulation's device."""
+        import torch
+
+        if not isinstance(buf, torch.Tensor) or not buf.is_cuda or buf.device != self.device:
+            raise ValueError(f"{what}: a tensor on {self.device} is required")
+        if not buf.is_contiguous():
+            raise ValueError(f"{what}: the tensor must be contiguous")
+        if buf.numel() * buf.element_size() < nbytes:
+            raise ValueError(f"{what}: {buf.numel() * buf.element_size()} bytes, {nbytes} needed")
+        if buf.data_ptr() % 256:
+            raise ValueError(f"{what}: the buffer must be 256-byte aligned")
+        return ctypes.c_void_p(buf.data_ptr())
 
     # ------------------------------------------------------------------
     def init_plasma(self, mu, n=None, uz=None, ux=None):
@@ -124,6 +146,12 @@ class Sim:
     def step(self, nsteps=1):
         with trace.marker("lbw_step"):
             self._check(self._lib.lbw_step(self._h, int(nsteps)))
+        return self
+
+    def set_nonfinite_check(self, every):
+        """Check the state for NaN / Inf after every ``every`` steps inside
+        step() (0: off); step() then raises LbwError(LBW_ERR_NONFINITE)."""
+        self._check(self._lib.lbw_set_nonfinite_check(self._h, int(every)))
         return self
 
     @property
@@ -180,20 +208,20 @@ class Sim:
         if out is None:
             with torch.cuda.stream(self.stream):
                 out = torch.empty(n, dtype=torch.uint8, device=self.device)
-        self._check(self._lib.lbw_save_state_device(self._h, ctypes.c_void_p(out.data_ptr())))
+        self._check(self._lib.lbw_save_state_device(self._h, self._device_buffer(out, n, "save_state_device")))
         return out
 
     def step_record(self, nsteps, buf, stride=None):
         """Advance nsteps steps, writing the canonical state after each into
         ``buf`` (a uint8 device tensor) at offsets 0, stride, 2 stride, ..."""
         stride = self.state_device_bytes() if stride is None else int(stride)
-        if buf.numel() < nsteps * stride:
-            raise ValueError("buffer too small for the records")
-        self._check(self._lib.lbw_step_record(self._h, int(nsteps), ctypes.c_void_p(buf.data_ptr()), stride))
+        p = self._device_buffer(buf, nsteps * stride, "step_record")
+        self._check(self._lib.lbw_step_record(self._h, int(nsteps), p, stride))
         return self
 
     def load_state_device(self, buf, step):
-        self._check(self._lib.lbw_load_state_device(self._h, ctypes.c_void_p(buf.data_ptr()), int(step)))
+        p = self._device_buffer(buf, self.state_device_bytes(), "load_state_device")
+        self._check(self._lib.lbw_load_state_device(self._h, p, int(step)))
         return self
 
     def save_state(self) -> bytes:

@@ -81,14 +81,16 @@ def test_adjoint_matches_kernel_fd_periodic_and_open():
     assert np.max(np.abs(g - g_fd)) <= 1e-6 * np.max(np.abs(g_fd))
 
 
-def test_adjoint_linear_regime_identity():
+@pytest.mark.parametrize("nslices", [8, 2000])
+def test_adjoint_linear_regime_identity(nslices):
     """For a weak driver the witness field is linear and homogeneous in the
     weights (a plasma at rest without driver stays at rest), so
-    loss(w) = sum_s w_s d loss / d w_s up to O(alpha^2)."""
+    loss(w) = sum_s w_s d loss / d w_s up to O(alpha^2). 2000 slices: more
+    slices than columns in the bunch window, most of them empty."""
     from paper_2309_04872_amd.adjoint import loss_and_grad
 
     cfg = _small(alpha=1e-6)
-    w = _weights(8, seed=3)
+    w = _weights(nslices, seed=3)
     loss, g = loss_and_grad(cfg, w, every=40)
     print("loss", loss, "w.g", float(w @ g), flush=True)
     assert abs(loss - w @ g) <= 1e-6 * abs(loss)

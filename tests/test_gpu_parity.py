@@ -566,3 +566,106 @@ def test_lec_recovery_random_states(dims, D):
         if dims == 2:
             assert np.abs(flat(s.read("ux")) - ref[:, 1]).max() <= 1e-13
         assert s.diagnostics()[6] == 0  # no recovery fallback
+
+
+# ---------------------------------------------------------------------------
+# FP16-deviation storage against the oracle (FP64). Stored values are
+# deviations from the rest state with 11-bit significands, so the error is set
+# by the FP16 rounding of each population every step, not by the recovery.
+
+TOL_FP16 = 1e-2
+
+
+@pytest.mark.parametrize("shape", ["lec_c2", "warmc_c3"])
+def test_parity_2d_fp16dev(shape):
+    """Slab, ragged multi-tile grids with the C2 (local equilibrium,
+    mu = 0.01, n_b/n0 = 1) and C3 (warm closure, mu = 0.05, n_b/n0 = 2)
+    parameters at delta = lambda_p/64; 60 steps."""
+    closure, mu, alpha = {"lec_c2": ("lec", 1e-2, 1.0), "warmc_c3": ("warmc", 5e-2, 2.0)}[shape]
+    nz, nx = 150, 37
+    d = 2 * np.pi / 64
+    print("2d fp16dev", shape, nz, nx, flush=True)
+    s, o = make_pair(2, nz, nx, delta=d, closure=closure, storage="fp16dev", mu=mu,
+                     driver=dict(alpha=alpha, sigma_z=1.0, sigma_x=0.5, z0=4.0))
+    s.step(60)
+    o.step(60)
+    compare(s, o, ["dn", "uz", "ux", "mz", "mx", "ez", "ex", "by"], TOL_FP16)
+
+
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+@pytest.mark.parametrize("path", ["single_steps", "persistent"])
+def test_parity_1d_fp16dev(closure, path):
+    """1D FP16-deviation storage, both the one-launch-per-step kernel (calls
+    of one step) and the persistent kernel with its multi-step passes (one
+    call); 600 nodes, 120 steps."""
+    nz = 600
+    n = workloads.density_noise((1, nz), 1e-3, 11)[0]
+    print("1d fp16dev", closure, path, flush=True)
+    s, o = make_pair(1, nz, closure=closure, storage="fp16dev", mu=0.02, n=n,
+                     driver=dict(alpha=0.3, sigma_z=0.5, z0=3.0))
+    if path == "single_steps":
+        for _ in range(120):
+            s.step(1)
+    else:
+        s.step(120)
+    o.step(120)
+    compare(s, o, ["dn", "uz", "mz", "ez"], TOL_FP16)
+
+
+# ---------------------------------------------------------------------------
+# The optional non-finite check inside lbw_step.
+
+@pytest.mark.parametrize("dims", [1, 2])
+def test_nonfinite_check_planted_nan(dims):
+    """A NaN planted in one node's scalars makes lbw_step return
+    LBW_ERR_NONFINITE at the first checked step (every 10 steps), with the
+    state canonical at that step; without the check the same call succeeds."""
+    from paper_2309_04872_amd.sim import LbwError, Sim
+
+    nz, nx = (300, 1) if dims == 1 else (96, 40)
+    K = 2 if dims == 1 else 3
+    A = np.zeros((K, nx, nz))
+    A[0] = 1.0
+    A[0, nx // 2, 37] = np.nan
+    s = Sim(dims, nz, nx, closure="lec")
+    s.init_moments(0.01, A)
+    s.set_nonfinite_check(10)
+    with pytest.raises(LbwError) as e:
+        s.step(35)
+    assert e.value.code == -5
+    assert s.step_count == 10
+    assert s.diagnostics(check=False)[5] > 0
+    s.set_nonfinite_check(0)
+    s.init_moments(0.01, A)
+    s.step(35)
+    assert s.step_count == 35
+
+
+def test_nonfinite_check_field_and_bits():
+    """A NaN set into one E_x slot after 20 clean steps is found at step 30;
+    on a clean driven run the check changes no bit of the result."""
+    from paper_2309_04872_amd.sim import LbwError, Sim
+
+    def run(check):
+        s = Sim(2, 96, 40, delta=2 * np.pi / 32, closure="warmc")
+        s.init_plasma(0.03)
+        s.init_driver(0.8, 1.0, 0.5, z0=4.0)
+        if check:
+            s.set_nonfinite_check(7)
+        s.step(23)
+        s.step(19)
+        return s, {q: s.read(q) for q in ("n", "uz", "ux", "thxz")} | {"ez": s.field("ez", at_nodes=False)}
+
+    _, a = run(False)
+    s, b = run(True)
+    for q in a:
+        assert np.array_equal(a[q], b[q]), q
+    s.set_nonfinite_check(10)
+    s.init_plasma(0.03)
+    s.step(20)
+    ex = s.field("ex", at_nodes=False)
+    ex[20, 50] = np.nan
+    s.set_field("ex", ex)
+    with pytest.raises(LbwError) as e:
+        s.step(25)
+    assert e.value.code == -5 and s.step_count == 30

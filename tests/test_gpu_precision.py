@@ -1,15 +1,19 @@
 """Precision variants at full grid size: FP32 and FP16 deviation storage
 against the FP64 run on the same GPU (the FP64 kernel matches the oracle to
 1e-10 on prefixes, see the parity tests; the oracle itself would need hours
-for these runs). Reported: per-field relative L2 of density, momentum and
-E_z.
+for these runs). Reported: per-field relative L2 of the density perturbation
+n - 1, the momentum densities and E_z. These are stated errors: each test
+guards the measured value (a regression bound about 1.5x above it); the
+FP32 parity tolerance of 1e-4 against the oracle applies to the parity tests.
 
 The warm-closure wake (4096 x 1024, n_b/n0 = 2, mu = 0.05) is compared over
-its first 400 steps: by step 500 the longitudinal pressure theta^zz has turned
-negative on the axis behind the bunch head and the run diverges (non-finite
-by step ~1400), in the FP64 kernel and in the oracle alike (the oracle's
-minimum theta^zz at steps 200 / 400 is 0.0109 / 0.00225, the kernel's the
-same). The local-equilibrium wake runs its full 8000 steps."""
+its first 400 steps (t = 3.9): near t = 4.5 (step ~459) its temperature
+theta^zz first turns negative on the axis behind the bunch head, and later
+the run diverges (non-finite near step 1400), in the FP64 kernel and in the
+oracle alike. On a reduced grid the oracle puts that onset at t = 4.5 for
+dt and dt / 2 (LB diffusion held fixed) and for delta / 2, so 400 steps is
+inside the closure's range of validity at every resolution tried. The
+local-equilibrium wake runs its full 8000 steps."""
 import json
 import os
 
@@ -20,7 +24,7 @@ from paper_2309_04872_amd import workloads
 
 pytestmark = pytest.mark.gpu
 
-FIELDS = ("n", "mz", "mx", "ez")
+FIELDS = ("dn", "mz", "mx", "ez")
 
 
 def _report(name, report):
@@ -40,7 +44,8 @@ def _run(w, storage, steps, extra=()):
     s.init_plasma(w["mu"])
     s.init_driver(w["alpha"], w["sigma_z"], w["sigma_x"], z0=w["z0"])
     s.step(steps)
-    out = {q: s.read(q) for q in ("n", "mz", "mx", *extra)}
+    out = {q: s.read(q) for q in ("mz", "mx", *extra)}
+    out["dn"] = s.read("n") - 1.0
     out["ez"] = s.field("ez")
     dg = s.diagnostics()
     del s
@@ -49,6 +54,25 @@ def _run(w, storage, steps, extra=()):
 
 WARM_STABLE_STEPS = 400
 
+# Stated errors (relative L2 against the FP64 run, measured on MI355X); the
+# tests guard each at 1.5x the measured value.
+MEASURED = {
+    "wake2d_warmc": {"fp32": {"dn": 3.8e-6, "mz": 2.0e-6, "mx": 1.1e-6, "ez": 1.4e-6},
+                     "fp16dev": {"dn": 1.34e-3, "mz": 8.4e-4, "mx": 6.6e-4, "ez": 2.1e-4}},
+    "wake2d_lec_fp32": {"fp32": {"dn": 7.3e-5, "mz": 5.8e-5, "mx": 7.4e-5, "ez": 7.7e-5},
+                        "fp16dev": {"dn": 2.3e-3, "mz": 1.66e-3, "mx": 1.64e-3, "ez": 1.68e-3}},
+    "wake_axi_lec": {"fp32": {"dn": 8.7e-5, "mz": 1.0e-4, "mx": 1.03e-4, "ez": 9.7e-5},
+                     "fp16dev": {"dn": 1.19e-3, "mz": 9.9e-4, "mx": 9.8e-4, "ez": 7.2e-4}},
+    "wake_axi_warmc": {"fp32": {"dn": 8.5e-5, "mz": 9.1e-5, "mx": 1.04e-4, "ez": 9.4e-5},
+                       "fp16dev": {"dn": 3.2e-3, "mz": 6.1e-3, "mx": 5.8e-3, "ez": 4.1e-3}},
+}
+
+
+def _guard(name, storage, errs):
+    ref = MEASURED[name][storage]
+    bad = {q: (e, ref[q]) for q, e in errs.items() if not e <= 1.5 * ref[q]}
+    assert not bad, (name, storage, "error above 1.5x the stated value", bad)
+
 
 def test_warm_wake_precision_variants():
     w = workloads.workload("wake2d_warmc")
@@ -56,13 +80,13 @@ def test_warm_wake_precision_variants():
     ref, dref = _run(w, "fp64", steps, extra=("thzz",))
     assert ref["thzz"].min() > 0.0
     report = {"workload": "wake2d_warmc", "steps": steps}
-    for storage, bound in (("fp32", 1e-4), ("fp16dev", 5e-2)):
+    for storage in ("fp32", "fp16dev"):
         got, dg = _run(w, storage, steps)
         assert dg[5] == 0
         errs = {q: float(np.linalg.norm(got[q] - ref[q]) / np.linalg.norm(ref[q])) for q in FIELDS}
         report[storage] = errs
         print(storage, errs, flush=True)
-        assert all(e <= bound for e in errs.values()), (storage, errs)
+        _guard("wake2d_warmc", storage, errs)
     _report("precision_wake2d_warmc.json", report)
 
 
@@ -72,13 +96,13 @@ def test_lec_wake_precision_variants_full_length():
     w = workloads.workload("wake2d_lec_fp32")
     ref, _ = _run(w, "fp64", w["steps"])
     report = {"workload": "wake2d_lec_fp32", "steps": w["steps"]}
-    for storage, bound in (("fp32", 1e-4), ("fp16dev", 5e-2)):
+    for storage in ("fp32", "fp16dev"):
         got, dg = _run(w, storage, w["steps"])
         assert dg[5] == 0
         errs = {q: float(np.linalg.norm(got[q] - ref[q]) / np.linalg.norm(ref[q])) for q in FIELDS}
         report[storage] = errs
         print(storage, errs, flush=True)
-        assert all(e <= bound for e in errs.values()), (storage, errs)
+        _guard("wake2d_lec_fp32", storage, errs)
     _report("precision_wake2d_lec.json", report)
 
 
@@ -87,17 +111,16 @@ def test_axi_production_precision_variants(closure):
     """The paper's axisymmetric production run (3000 x 600, mu = 0.04,
     Q~ = 0.5, all 30 000 steps) in FP32 and FP16 deviation storage against
     FP64. Over 30 000 steps the FP32 rounding reaches about 1e-4 in the
-    momenta (1.0e-4 measured for the local-equilibrium closure), so the FP32
-    bound here is 3e-4."""
+    momenta (stated errors in MEASURED)."""
     w = workloads.workload("wake_axi_" + closure)
     print("axi precision", closure, flush=True)
     ref, _ = _run(w, "fp64", w["steps"])
     report = {"workload": "wake_axi_" + closure, "steps": w["steps"]}
-    for storage, bound in (("fp32", 3e-4), ("fp16dev", 5e-2)):
+    for storage in ("fp32", "fp16dev"):
         got, dg = _run(w, storage, w["steps"])
         assert dg[5] == 0
         errs = {q: float(np.linalg.norm(got[q] - ref[q]) / np.linalg.norm(ref[q])) for q in FIELDS}
         report[storage] = errs
         print(storage, errs, flush=True)
-        assert all(e <= bound for e in errs.values()), (storage, errs)
+        _guard("wake_axi_" + closure, storage, errs)
     _report(f"precision_wake_axi_{closure}.json", report)
