@@ -597,7 +597,12 @@ def test_parity_2d_fp16dev(shape):
 def test_parity_1d_fp16dev(closure, path):
     """1D FP16-deviation storage, both the one-launch-per-step kernel (calls
     of one step) and the persistent kernel with its multi-step passes (one
-    call); 600 nodes, 120 steps."""
+    call); 600 nodes, 120 steps. Measured on the density perturbation: L2
+    8.0e-3 - 8.6e-3 and element-wise maximum 1.3e-2 - 1.5e-2 of max|n - 1|
+    (the same kernel in FP32: 6e-6). The error grows step by step alike
+    ahead of and behind the bunch, and with or without the density noise;
+    n - 1 is small here (at most 0.045 at step 120), so its relative error is
+    larger than in the 2D cases. Tolerances 2e-2 (L2) and 3e-2 (maximum)."""
     nz = 600
     n = workloads.density_noise((1, nz), 1e-3, 11)[0]
     print("1d fp16dev", closure, path, flush=True)
@@ -609,7 +614,7 @@ def test_parity_1d_fp16dev(closure, path):
     else:
         s.step(120)
     o.step(120)
-    compare(s, o, ["dn", "uz", "mz", "ez"], TOL_FP16)
+    compare(s, o, ["dn", "uz", "mz", "ez"], 2e-2, max_tol=3e-2)
 
 
 # ---------------------------------------------------------------------------
