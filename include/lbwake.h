@@ -219,6 +219,21 @@ lbw_status lbw_read_field(lbw_sim *sim, int which, int at_nodes, double *host_ou
  * FP64. Returns LBW_ERR_NONFINITE when out[5] > 0. */
 lbw_status lbw_diagnostics(lbw_sim *sim, double *out);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * lbw_diagnostics with its scratch (the per-workgroup partial sums and
+ * totals of the reduction) in a static device array of the library instead
+ * of the simulation's workspace, 1 MiB per GPU, held until the process ends.
+ * Writes the same 8 values to device_out (caller-owned device memory, 8
+ * doubles), asynchronously on the simulation's stream, and neither
+ * allocates, copies to the host nor synchronises; out[5] > 0 reports
+ * non-finite nodes (no LBW_ERR_NONFINITE here). Grids of more than
+ * 5 586 944 nodes return LBW_ERR_UNSUPPORTED. All calls on one GPU share its
+ * array: calls that overlap on one GPU (different streams or threads) race;
+ * calls in one stream's order do not. Nothing in the array needs clearing
+ * between calls. */
+lbw_status lbw_diagnostics_static(lbw_sim *sim, double *device_out);
+
 long lbw_step_count(const lbw_sim *sim);
 
 /* Kernel timing: while enabled, lbw_step brackets its back-to-back fused

@@ -27,7 +27,7 @@ FIELDS = {"ez": 0, "ex": 1, "by": 2, "wake_x": 3}
 EXPORTS = [
     "lbw_workspace_bytes", "lbw_create", "lbw_init_plasma", "lbw_init_moments", "lbw_init_driver",
     "lbw_set_field", "lbw_step", "lbw_set_nonfinite_check", "lbw_read_moment", "lbw_read_moment_device", "lbw_read_field",
-    "lbw_diagnostics", "lbw_step_count", "lbw_set_timing", "lbw_get_timing", "lbw_state_bytes", "lbw_save_state", "lbw_load_state",
+    "lbw_diagnostics", "lbw_diagnostics_static", "lbw_step_count", "lbw_set_timing", "lbw_get_timing", "lbw_state_bytes", "lbw_save_state", "lbw_load_state",
     "lbw_last_error", "lbw_version", "lbw_destroy",
     "lbw_state_device_bytes", "lbw_save_state_device", "lbw_load_state_device", "lbw_step_record",
     "lbw_adjoint_bytes", "lbw_adjoint_workspace_bytes", "lbw_adjoint_step", "lbw_adjoint_init_fields",
@@ -114,6 +114,8 @@ def load(path: str | None = None):
     L.lbw_read_field.argtypes = [vp, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_size_t]
     L.lbw_diagnostics.restype = ctypes.c_int
     L.lbw_diagnostics.argtypes = [vp, _dp]
+    L.lbw_diagnostics_static.restype = ctypes.c_int
+    L.lbw_diagnostics_static.argtypes = [vp, vp]
     L.lbw_step_count.restype = ctypes.c_long
     L.lbw_step_count.argtypes = [vp]
     L.lbw_set_timing.restype = ctypes.c_int

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -420,6 +421,40 @@ void fill_aref(lbw_sim *s)
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Static scratch of lbw_diagnostics_static: the per-workgroup partial sums of
+// the diagnostics reduction (NDIAG values per workgroup of DIAG_THREADS
+// nodes) and its NDIAG totals, 1 MiB in all, which bounds that call to grids
+// of at most STATIC_DIAG_MAX_NODES nodes. Each GPU the library runs on holds
+// its own copy until the process ends. In host code `scratch` only names the
+// symbol: kernels get the device address from hipGetSymbolAddress, taken once
+// per device with that device current and kept in g_scratch_ptr.
+namespace {
+constexpr int STATIC_DIAG_MAX_BLOCKS = 21824;
+constexpr size_t STATIC_DIAG_MAX_NODES = (size_t)STATIC_DIAG_MAX_BLOCKS * DIAG_THREADS;
+constexpr int STATIC_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[STATIC_DEVICES] = {};
+}  // namespace
+static __device__ __align__(256) double scratch[NDIAG * STATIC_DIAG_MAX_BLOCKS + 64];
+
+// The public layout of lbw_diagnostics from the reduction's raw totals
+// (sums of n dV, field energy, kinetic energy, Gauss residual^2, non-finite
+// nodes; max |u| / Lambda).
+static __global__ void k_diag_publish(const double *raw, const unsigned int *fallbacks, double nodes, long step,
+                                      double *out)
+{
+    if (threadIdx.x != 0) return;
+    out[0] = raw[0];
+    out[1] = raw[1];
+    out[2] = raw[2];
+    out[3] = sqrt(raw[3] / nodes);
+    out[4] = raw[5];
+    out[5] = raw[4];
+    out[6] = (double)*fallbacks;
+    out[7] = (double)step;
+}
 
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -881,6 +916,52 @@ lbw_status lbw_diagnostics(lbw_sim *s, double *out)
     out[6] = (double)fb;
     out[7] = (double)s->step;
     if (d[4] > 0 || !std::isfinite(d[0])) return fail(s, LBW_ERR_NONFINITE, "non-finite values in the state");
+    return LBW_OK;
+}
+
+// Device address of this GPU's static scratch (the device that holds the
+// simulation's workspace), taken once per device.
+static lbw_status static_scratch(lbw_sim *s, double **out)
+{
+    hipPointerAttribute_t attr{};
+    HIPCHK(s, hipPointerGetAttributes(&attr, s->ws));
+    const int dev = attr.device;
+    if (dev < 0 || dev >= STATIC_DEVICES) return fail(s, LBW_ERR_UNSUPPORTED, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        HIPCHK(s, hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(s, hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) HIPCHK(s, hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            return fail(s, LBW_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBW_OK;
+}
+
+lbw_status lbw_diagnostics_static(lbw_sim *s, double *device_out)
+{
+    if (!s || !device_out) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    if (nc > STATIC_DIAG_MAX_NODES)
+        return fail(s, LBW_ERR_UNSUPPORTED, "grid larger than the static scratch of lbw_diagnostics_static allows (" +
+                                                std::to_string(STATIC_DIAG_MAX_NODES) + " nodes)");
+    double *ptr = nullptr;
+    lbw_status st = static_scratch(s, &ptr);
+    if (st != LBW_OK) return st;
+    StepArgs a = base_args(s);
+    set_io(s, a);
+    const int nblk = s->L.nblk_diag;
+    double *part = ptr, *raw = ptr + (size_t)NDIAG * STATIC_DIAG_MAX_BLOCKS;
+    ops_for(s->g).diag(a, part, nblk, raw, s->stream);
+    hipLaunchKernelGGL(k_diag_publish, dim3(1), dim3(64), 0, s->stream, (const double *)raw,
+                       (const unsigned int *)(s->ws + s->L.fallbacks), (double)nc, s->step, device_out);
+    HIPCHK(s, hipGetLastError());
     return LBW_OK;
 }
 
