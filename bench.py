@@ -259,7 +259,7 @@ def batch_bytes_per_step(insts):
     return sum(d["nz"] * bytes_per_lu(1, d["closure"], "fp64") for d in insts)
 
 
-BATCH_TRAFFIC_PER_STEP = 33.55e6
+BATCH_TRAFFIC_PER_STEP = None  # re-measured after the kernel's arguments changed (profiles/k_batch1d_batch1d_scan.md)
 BATCH_PASS_DEPTH = 16
 
 
@@ -352,7 +352,13 @@ def bench_batch(args):
     steps = args.steps if args.steps is not None else workloads.BATCH_SCAN["steps"]
     cells = sum(d["nz"] for d in insts)
     b = Batch(insts).init()
-    threads, cpt = b.autotune(probe_steps=20)
+    if args.batch_config:
+        # a fixed launch configuration instead of the autotuner (for profiled runs)
+        threads, cpt = (int(v) for v in args.batch_config.split(","))
+        b.set_config(threads, cpt)
+    else:
+        threads, cpt = b.autotune(probe_steps=20)
+    sched = b.schedule()
     if args.warmup:
         b.step(args.warmup, graph=True)
     torch.cuda.synchronize()
@@ -398,13 +404,16 @@ def bench_batch(args):
             "nz_range": [min(d["nz"] for d in insts), max(d["nz"] for d in insts)],
             "closures": "alternating lec / warmc", "populations": "fp64", "delta": "lambda_p/128",
             "steps_per_run": steps, "launches": 1, "hip_graph": True,
-            "autotuned": {"threads": threads, "nodes_per_thread": cpt}, "parallelism": "single GPU",
+            "launch_config": {"threads": threads, "nodes_per_thread": cpt, "split": sched[2],
+                              "workgroups": sched[3], "autotuned": not args.batch_config},
+            "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             # measured on the full 4096-step launch (the pass schedule depends on the step count)
-            "traffic": traffic_per_step * steps if steps == workloads.BATCH_SCAN["steps"] else None,
+            "traffic": (traffic_per_step * steps
+                        if traffic_per_step and steps == workloads.BATCH_SCAN["steps"] else None),
             "kernel": "k_batch1d",
             "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
             "kernel_avg_us": k_ms * 1e3, "bytes_per_step": bps, "sweeps": sweeps, "launches": 1,
@@ -415,8 +424,9 @@ def bench_batch(args):
         },
         "wall_s": wall,
         "diagnostics": {"nonfinite_instances": int((bad > 0).sum())},
-        "sequential_fp64": sequential_fp64(insts, steps),
     }
+    if not args.no_sequential:
+        line["sequential_fp64"] = sequential_fp64(insts, steps)
     b.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_batch(insts, args.cpu_budget)
@@ -513,6 +523,10 @@ def main():
     ap.add_argument("--workload", default="wake2d_warmc")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32 / FP16-dev comparison of the default workload")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batch1d_scan: skip the single-run FP64 comparison")
+    ap.add_argument("--batch-config", default=None,
+                    help="batch1d_scan: threads,nodes_per_thread instead of the autotuner")
     ap.add_argument("--storage", default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)

@@ -310,13 +310,13 @@ lbw_status lbw_adjoint_init_fields(lbw_sim *sim, const double *adj, double *grad
  * of lbw_step (Sec. 2.1-2.2 streaming and collision, Sec. 3.1 / Sec. 4.1
  * recoveries and forces, Sec. 5 field update and driver); the instances only
  * share the launch. lbw_batch_step runs all requested steps of every
- * instance inside one persistent kernel launch: one workgroup owns one
- * instance for the whole launch and advances it in passes separated by
- * workgroup barriers (after the first step, passes of 16 steps and then pairs
- * of steps, the state read and written once per pass), so no instance ever
- * waits on another
- * and the launch needs no co-residency. Workgroups take instances longest
- * first.
+ * instance inside one persistent kernel launch: by default one workgroup
+ * owns one instance for the whole launch and advances it in passes separated
+ * by workgroup barriers (after the first step, passes of 16 steps and then
+ * pairs of steps, the state read and written once per pass), so no instance
+ * ever waits on another and the launch needs no co-residency; the split
+ * schedule (lbw_batch_set_schedule) shares long instances among several
+ * co-resident workgroups. Workgroups take instances longest first.
  *
  * The workspace is caller-owned device memory (256-byte aligned) of at least
  * lbw_batch_workspace_bytes(); the library allocates no device memory. It
@@ -364,15 +364,33 @@ lbw_status lbw_batch_init(lbw_batch *b, const double *n_init);
  * HIP graph captured on first use for this (nsteps, configuration). Returns
  * without synchronising. */
 lbw_status lbw_batch_step(lbw_batch *b, int nsteps, int use_graph);
-/* Launch configuration of the persistent kernel: threads per workgroup and
- * nodes per thread per pass, one of (256, 1), (256, 2), (512, 1), (512, 2),
- * (1024, 1); the default is (1024, 1). LBW_ERR_ARG for any other pair. */
+/* Launch configuration of the persistent kernel with one workgroup per
+ * instance: threads per workgroup and nodes per thread per pass, one of
+ * (256, 1), (256, 2), (512, 1), (512, 2), (1024, 1); the default is
+ * (1024, 1). LBW_ERR_ARG for any other pair. get_config reports the shape of
+ * the current configuration, whatever its schedule. */
 lbw_status lbw_batch_set_config(lbw_batch *b, int threads, int nodes_per_thread);
 lbw_status lbw_batch_get_config(const lbw_batch *b, int *threads, int *nodes_per_thread);
-/* Autotuner: runs probe_steps steps under every configuration from the same
- * state (snapshot and restore inside the workspace), keeps the fastest and
- * returns it. The state afterwards is bit-for-bit the state before.
- * Synchronises the stream. */
+/* Schedule of the launch. split = 0: one workgroup per instance (as
+ * lbw_batch_set_config), so the launch is bound by the longest instance.
+ * split = 1, for the shapes (256, 2), (512, 1), (512, 2), (1024, 1): as many
+ * workgroups as the occupancy query proves co-resident (a cooperative
+ * launch); instance i gets ceil(tiles_i / L) of them for the smallest L that
+ * fits (tiles_i: tiles of its deep passes), they take contiguous runs of
+ * every sweep's tiles and meet at a barrier of their own after each sweep
+ * (the only waits between workgroups, safe because all are resident).
+ * Results are the same bits under every schedule. LBW_ERR_UNSUPPORTED when
+ * fewer workgroups than instances can be resident or the device has no
+ * cooperative launch. get_schedule also returns the workgroups a launch
+ * uses. */
+lbw_status lbw_batch_set_schedule(lbw_batch *b, int threads, int nodes_per_thread, int split);
+lbw_status lbw_batch_get_schedule(const lbw_batch *b, int *threads, int *nodes_per_thread, int *split,
+                                  int *workgroups);
+/* Autotuner: runs probe_steps steps under every configuration (shape and
+ * schedule) the device can launch, from the same state (snapshot and
+ * restore inside the workspace), keeps the fastest and returns its shape
+ * (lbw_batch_get_schedule tells its schedule). The state afterwards is
+ * bit-for-bit the state before. Synchronises the stream. */
 lbw_status lbw_batch_autotune(lbw_batch *b, int probe_steps, int *threads, int *nodes_per_thread);
 /* One observable of instance inst into host_out (count = that instance's
  * nz): an lbw_moment, or LBW_BATCH_EZ. Synchronises the stream. */

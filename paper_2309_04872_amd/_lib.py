@@ -32,7 +32,8 @@ EXPORTS = [
     "lbw_state_device_bytes", "lbw_save_state_device", "lbw_load_state_device", "lbw_step_record",
     "lbw_adjoint_bytes", "lbw_adjoint_workspace_bytes", "lbw_adjoint_step", "lbw_adjoint_init_fields",
     "lbw_batch_workspace_bytes", "lbw_batch_create", "lbw_batch_init", "lbw_batch_step",
-    "lbw_batch_set_config", "lbw_batch_get_config", "lbw_batch_autotune", "lbw_batch_read",
+    "lbw_batch_set_config", "lbw_batch_get_config", "lbw_batch_set_schedule", "lbw_batch_get_schedule",
+    "lbw_batch_autotune", "lbw_batch_read",
     "lbw_batch_nonfinite", "lbw_batch_step_count", "lbw_batch_get_timing", "lbw_batch_last_error",
     "lbw_batch_destroy",
 ]
@@ -164,6 +165,10 @@ def load(path: str | None = None):
     L.lbw_batch_set_config.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.lbw_batch_get_config.restype = ctypes.c_int
     L.lbw_batch_get_config.argtypes = [vp, ip, ip]
+    L.lbw_batch_set_schedule.restype = ctypes.c_int
+    L.lbw_batch_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.lbw_batch_get_schedule.restype = ctypes.c_int
+    L.lbw_batch_get_schedule.argtypes = [vp, ip, ip, ip, ip]
     L.lbw_batch_autotune.restype = ctypes.c_int
     L.lbw_batch_autotune.argtypes = [vp, ctypes.c_int, ip, ip]
     L.lbw_batch_read.restype = ctypes.c_int

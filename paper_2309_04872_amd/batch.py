@@ -66,9 +66,10 @@ class Batch:
             self._lib.lbw_batch_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # during interpreter shutdown the HIP runtime may already be gone
-        if sys.is_finalizing():
+        # (module globals such as sys may be None by then, hence the default)
+        if _finalizing():
             return
         try:
             self.close()
@@ -102,6 +103,19 @@ class Batch:
         t, c = ctypes.c_int(), ctypes.c_int()
         self._check(self._lib.lbw_batch_get_config(self._h, ctypes.byref(t), ctypes.byref(c)))
         return t.value, c.value
+
+    def set_schedule(self, threads, nodes_per_thread=1, split=False):
+        """Launch shape and schedule; split=True shares long instances among
+        several co-resident workgroups (cooperative launch)."""
+        self._check(self._lib.lbw_batch_set_schedule(self._h, int(threads), int(nodes_per_thread), int(bool(split))))
+        return self
+
+    def schedule(self):
+        """(threads, nodes per thread, split, workgroups of a launch)."""
+        v = [ctypes.c_int() for _ in range(4)]
+        self._check(self._lib.lbw_batch_get_schedule(self._h, *[ctypes.byref(x) for x in v]))
+        t, c, sp, wg = (x.value for x in v)
+        return t, c, bool(sp), wg
 
     def autotune(self, probe_steps=20):
         t, c = ctypes.c_int(), ctypes.c_int()

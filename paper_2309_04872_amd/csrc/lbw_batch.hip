@@ -63,13 +63,49 @@ struct BState {
     int pad[2];
 };
 
+// Work of each workgroup: items woff[w] .. woff[w + 1] - 1 of `items`, each
+// (instance, part, parts), run one after another. With one workgroup per
+// instance every list holds one whole instance (part 0 of 1), longest first.
+// Under the split schedule a workgroup's list starts with at most one part of
+// a shared instance, followed by whole short instances, so that all parts of
+// every shared instance run at the same time.
 struct BatchArgs {
     const BInst *inst;
-    const int *order;  // workgroup -> instance, longest first
+    const int *woff, *items;
+    unsigned int *bar;  // per instance (arrivals, generation) of its parts' barrier
     double *pop0, *pop1, *ez, *lag;
     BState *st;
     int nsteps;
 };
+
+// Barrier among the `parts` workgroups that share one instance under the
+// split schedule. Only valid when all of them are resident at once, which the
+// cooperative launch of that schedule guarantees. Arrivals count up to parts
+// and return to zero; the last arrival bumps the generation the others wait
+// on, so the barrier needs no reset between launches. The workgroup barrier
+// first makes every wave's stores complete in L2 (the L1 writes through);
+// thread 0's agent-scope release then writes the L2 back for the other XCDs,
+// and its acquire invalidates this CU's L1 and the L2's stale lines before
+// the second workgroup barrier lets the other waves load. One thread per
+// workgroup does the cache maintenance: it acts on whole caches.
+__device__ __forceinline__ void instance_barrier(unsigned int *bar, int parts)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == (unsigned int)parts - 1u) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+                __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
 
 // LDS for the recovered quantities whose z-derivatives the forces need:
 // LEC phi | WARMC theta^0z, theta^zz, lambda u_z, one value per slot of a
@@ -387,8 +423,13 @@ __device__ __forceinline__ int finish_pass(const BInst &P, const double *src, do
     return bad;
 }
 
-template <int CL, int T, int CPT>
-__device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds<T, CPT> &sh)
+// part / parts: under the split schedule the instance's workgroups take
+// contiguous runs of every sweep's tiles and meet at instance_barrier after
+// each sweep (the next sweep reads ring nodes another workgroup wrote); with
+// parts = 1 the workgroup barrier that ends every pass is enough.
+template <int CL, int T, int CPT, bool SPLIT>
+__device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds<T, CPT> &sh, int part, int parts,
+                             unsigned int *bar)
 {
     constexpr int W = pass_width<T, CPT>();
     constexpr int W2 = passs_width<T, CPT, 2>();
@@ -402,6 +443,24 @@ __device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds
     double *pop[2] = {a.pop0 + P.pop, a.pop1 + P.pop};
     double *ez[2] = {a.ez + P.fld, a.ez + P.fld + nzp};
     double *lag[2] = {a.lag + P.lag, a.lag + P.lag + (CL == WARMC ? NLAG1 * nzp : 0)};
+    // this part's run [b0, b1) of a sweep's tile bases (tiles of `width` nodes)
+    auto span = [&](int width, int &b0, int &b1) {
+        if constexpr (!SPLIT) {
+            b0 = 0;
+            b1 = P.nz;
+        } else {
+            const long nt = (P.nz + width - 1) / width;
+            b0 = (int)(nt * part / parts) * width;
+            b1 = (int)(nt * (part + 1) / parts) * width;
+            if (b1 > P.nz) b1 = P.nz;
+        }
+    };
+    auto sweep_done = [&]() {
+        if constexpr (SPLIT)
+            if (parts > 1) instance_barrier(bar, parts);
+    };
+    if (SPLIT && parts > 1 && part == 0 && threadIdx.x == 0) st->nonfinite = 0;  // summed by every part below
+    int b0, b1;
     // schedule: the first step from the canonical state, then passes of
     // BATCH_DEPTH steps, pairs of steps for what is left, then a last single
     // step if one is left. Every pass ends on a barrier, so each step's stores
@@ -409,81 +468,235 @@ __device__ void run_instance(const BatchArgs &a, const BInst &P, BState *st, Lds
     // neighbours.
     long s = 0;
     if (nsteps > 0) {
-        for (int base = 0; base < P.nz; base += W)
+        span(W, b0, b1);
+        for (int base = b0; base < b1; base += W)
             step_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez[ec], lag[ec], base, false, false, lag_init,
                                   step0, sh);
+        sweep_done();
         cur ^= 1;
         s = 1;
     }
     for (; s > 0 && s + BATCH_DEPTH <= nsteps; s += BATCH_DEPTH) {
-        for (int base = 0; base < P.nz; base += WD)
+        span(WD, b0, b1);
+        for (int base = b0; base < b1; base += WD)
             step_passs<CL, T, CPT, BATCH_DEPTH>(P, pop[cur], pop[cur ^ 1], ez[ec], ez[ec ^ 1], lag[ec],
                                                 lag[ec ^ 1], base, step0 + s, sh);
+        sweep_done();
         cur ^= 1;
         ec ^= 1;
     }
     for (; s > 0 && s + 2 <= nsteps; s += 2) {
-        for (int base = 0; base < P.nz; base += W2)
+        span(W2, b0, b1);
+        for (int base = b0; base < b1; base += W2)
             step_passs<CL, T, CPT, 2>(P, pop[cur], pop[cur ^ 1], ez[ec], ez[ec ^ 1], lag[ec], lag[ec ^ 1], base,
                                       step0 + s, sh);
+        sweep_done();
         cur ^= 1;
         ec ^= 1;
     }
     if (s < nsteps) {
-        for (int base = 0; base < P.nz; base += W)
+        span(W, b0, b1);
+        for (int base = b0; base < b1; base += W)
             step_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez[ec], lag[ec], base, true, true, false, step0 + s,
                                   sh);
+        sweep_done();
         cur ^= 1;
     }
     if (threadIdx.x == 0) sh.bad = 0;
     __syncthreads();
     int bad = 0;
-    for (int base = 0; base < P.nz; base += WF)
+    span(WF, b0, b1);
+    for (int base = b0; base < b1; base += WF)
         bad += finish_pass<CL, T, CPT>(P, pop[cur], pop[cur ^ 1], ez[ec], base, step0 + nsteps);
     if (bad) atomicAdd(&sh.bad, bad);
     __syncthreads();
     if (threadIdx.x == 0) {
-        st->cur = cur ^ 1;
-        st->ecur = ec;
-        st->step = step0 + nsteps;
-        st->lag_valid = 1;
-        st->nonfinite = sh.bad;
+        if (SPLIT && parts > 1) {
+            if (sh.bad) atomicAdd(&st->nonfinite, sh.bad);
+        } else {
+            st->nonfinite = sh.bad;
+        }
+        if (part == 0) {
+            st->cur = cur ^ 1;
+            st->ecur = ec;
+            st->step = step0 + nsteps;
+            st->lag_valid = 1;
+        }
     }
 }
 
+// One workgroup per instance (workgroup w runs the instance of work item w).
 template <int T, int CPT>
 __global__ __launch_bounds__(T) void k_batch1d(BatchArgs a)
 {
     __shared__ Lds<T, CPT> sh;
-    const int i = a.order[blockIdx.x];
+    const int i = a.items[3 * blockIdx.x];
     const BInst P = a.inst[i];
     if (P.closure == LEC)
-        run_instance<LEC, T, CPT>(a, P, a.st + i, sh);
+        run_instance<LEC, T, CPT, false>(a, P, a.st + i, sh, 0, 1, nullptr);
     else
-        run_instance<WARMC, T, CPT>(a, P, a.st + i, sh);
+        run_instance<WARMC, T, CPT, false>(a, P, a.st + i, sh, 0, 1, nullptr);
 }
 
-struct Config {
-    int threads, cpt;
-};
-// (1024 threads with two nodes each would spill registers at the 128-VGPR
-// limit of 1024-thread workgroups)
-const Config CONFIGS[] = {{256, 1}, {256, 2}, {512, 1}, {512, 2}, {1024, 1}};
-constexpr int NCONFIG = sizeof(CONFIGS) / sizeof(CONFIGS[0]);
-
-void launch_config(int ci, const BatchArgs &a, int nblocks, hipStream_t s)
+// Split schedule: each workgroup runs its work list (a part of a shared
+// instance first, then whole short instances).
+template <int T, int CPT>
+__global__ __launch_bounds__(T) void k_batch1d_split(BatchArgs a)
 {
-    switch (ci) {
-    case 0: hipLaunchKernelGGL((k_batch1d<256, 1>), dim3(nblocks), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_batch1d<256, 2>), dim3(nblocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_batch1d<512, 1>), dim3(nblocks), dim3(512), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_batch1d<512, 2>), dim3(nblocks), dim3(512), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_batch1d<1024, 1>), dim3(nblocks), dim3(1024), 0, s, a); break;
+    __shared__ Lds<T, CPT> sh;
+    const int end = a.woff[blockIdx.x + 1];
+    for (int it = a.woff[blockIdx.x]; it < end; ++it) {
+        const int i = a.items[3 * it], part = a.items[3 * it + 1], parts = a.items[3 * it + 2];
+        const BInst P = a.inst[i];
+        unsigned int *bar = a.bar + 2 * (size_t)i;
+        if (P.closure == LEC)
+            run_instance<LEC, T, CPT, true>(a, P, a.st + i, sh, part, parts, bar);
+        else
+            run_instance<WARMC, T, CPT, true>(a, P, a.st + i, sh, part, parts, bar);
+        __syncthreads();  // the next item reuses the LDS
     }
 }
 
+// Launch configurations: threads per workgroup, nodes per thread per pass,
+// and the schedule: one workgroup per instance (split = 0; a plain launch,
+// no workgroup waits on another), or split = 1: every workgroup that can be
+// resident at once, the long instances shared by several of them that meet
+// at a barrier after each sweep (a cooperative launch, whose grid the
+// occupancy query proves co-resident).
+// (1024 threads with two nodes each would spill registers at the 128-VGPR
+// limit of 1024-thread workgroups)
+struct Config {
+    int threads, cpt, split;
+};
+const Config CONFIGS[] = {{256, 1, 0}, {256, 2, 0}, {512, 1, 0}, {512, 2, 0}, {1024, 1, 0},
+                          {256, 2, 1}, {512, 1, 1}, {512, 2, 1}, {1024, 1, 1}};
+constexpr int NCONFIG = sizeof(CONFIGS) / sizeof(CONFIGS[0]);
+constexpr int MAX_SPLIT_WG = 8192;  // workgroups of a split launch (resident ones only)
+
+template <int T, int CPT> const void *kernel_of(bool split)
+{
+    return split ? (const void *)k_batch1d_split<T, CPT> : (const void *)k_batch1d<T, CPT>;
+}
+const void *config_kernel(int ci)
+{
+    const Config &c = CONFIGS[ci];
+    const bool sp = c.split != 0;
+    if (c.threads == 256) return c.cpt == 1 ? kernel_of<256, 1>(sp) : kernel_of<256, 2>(sp);
+    if (c.threads == 512) return c.cpt == 1 ? kernel_of<512, 1>(sp) : kernel_of<512, 2>(sp);
+    return kernel_of<1024, 1>(sp);
+}
+
+hipError_t launch_config(int ci, const BatchArgs &a, int nblocks, hipStream_t s)
+{
+    const Config &c = CONFIGS[ci];
+    BatchArgs aa = a;
+    void *args[] = {&aa};
+    if (c.split) return hipLaunchCooperativeKernel(config_kernel(ci), dim3(nblocks), dim3(c.threads), args, 0, s);
+    return hipLaunchKernel(config_kernel(ci), dim3(nblocks), dim3(c.threads), args, 0, s);
+}
+
+// Deep-pass tile width of a configuration (nodes a workgroup owns per pass).
+int deep_width(const Config &c) { return c.threads * c.cpt - 4 * BATCH_DEPTH + 2; }
+
+// Workgroups of configuration ci that can all be resident (0: no
+// cooperative launch on this device).
+int resident_workgroups(int ci)
+{
+    int dev = 0, coop = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, config_kernel(ci), CONFIGS[ci].threads, 0) != hipSuccess)
+        return 0;
+    return per * cus;
+}
+
+// Work lists, as woff (nwg + 1 offsets) followed by the (instance, part,
+// parts) items.
+struct Plan {
+    std::vector<int> woff, items;
+};
+
+// One workgroup per instance, longest first.
+Plan plan_whole(const std::vector<int> &order)
+{
+    Plan p;
+    p.woff.push_back(0);
+    for (int i : order) {
+        p.items.insert(p.items.end(), {i, 0, 1});
+        p.woff.push_back((int)p.items.size() / 3);
+    }
+    return p;
+}
+
+// Split schedule on nwg workgroups for the instances' deep-sweep tile counts
+// (the sweeps of one launch all split in the same proportions): the smallest
+// L for which instances of more than L tiles, cut into ceil(tiles / L) parts
+// that each lead a workgroup, and the remaining whole instances, packed
+// largest first into the least loaded workgroups, leave no workgroup with
+// more than L tiles. L is then the most tiles any workgroup sweeps (one
+// workgroup per instance gives the largest instance's count).
+Plan plan_split(const std::vector<lbw_instance_desc> &d, const std::vector<int> &order, int width, int nwg)
+{
+    const int n = (int)d.size();
+    std::vector<int> tiles(n);
+    int hi = 1, lo = 1;
+    long total = 0;
+    for (int i = 0; i < n; ++i) {
+        tiles[i] = (d[i].nz + width - 1) / width;
+        hi = std::max(hi, tiles[i]);
+        total += tiles[i];
+    }
+    lo = std::max<long>(1, (total + nwg - 1) / nwg);
+    // try(L): the lists, or empty when L does not fit
+    auto attempt = [&](int L, std::vector<std::vector<int>> &lists) {
+        lists.assign(nwg, {});
+        std::vector<int> load(nwg, 0);
+        int w = 0;
+        for (int i : order) {  // longest first: the shared instances lead their lists
+            if (tiles[i] <= L) continue;
+            const int parts = (tiles[i] + L - 1) / L;
+            for (int j = 0; j < parts; ++j) {
+                if (w >= nwg) return false;
+                lists[w] = {i, j, parts};
+                load[w] = (int)((long)tiles[i] * (j + 1) / parts - (long)tiles[i] * j / parts);
+                ++w;
+            }
+        }
+        for (int i : order) {
+            if (tiles[i] > L) continue;
+            int best = 0;
+            for (int k = 1; k < nwg; ++k)
+                if (load[k] < load[best]) best = k;
+            if (load[best] + tiles[i] > L) return false;
+            lists[best].insert(lists[best].end(), {i, 0, 1});
+            load[best] += tiles[i];
+        }
+        return true;
+    };
+    std::vector<std::vector<int>> lists, best_lists;
+    if (!attempt(hi, best_lists)) return plan_whole(order);  // fewer workgroups than instances
+    while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (attempt(mid, lists)) {
+            hi = mid;
+            best_lists = lists;
+        } else {
+            lo = mid + 1;
+        }
+    }
+    Plan p;
+    p.woff.push_back(0);
+    for (const auto &l : best_lists) {
+        if (l.empty()) continue;  // unused workgroups are not launched
+        p.items.insert(p.items.end(), l.begin(), l.end());
+        p.woff.push_back((int)p.items.size() / 3);
+    }
+    return p;
+}
+
 struct BLayout {
-    size_t inst, order, st, pop[2], ez, lag, snap_pop, snap_ez, snap_lag, snap_st, zeros, total;
+    size_t inst, plan[2], bar, st, pop[2], ez, lag, snap_pop, snap_ez, snap_lag, snap_st, zeros, total;
     size_t pop_elems, fld_elems, lag_elems;
 };
 
@@ -520,7 +733,13 @@ BLayout make_blayout(const lbw_instance_desc *d, int n)
     L.lag_elems = le;
     size_t off = 0;
     L.inst = off; off += align_up(n * sizeof(BInst));
-    L.order = off; off += align_up(n * sizeof(int));
+    // work lists: one workgroup per instance (plan[0]) and the split schedule
+    // (plan[1]): at most MAX_SPLIT_WG + 1 offsets and n + MAX_SPLIT_WG items
+    for (int k = 0; k < 2; ++k) {
+        L.plan[k] = off;
+        off += align_up(((size_t)MAX_SPLIT_WG + 1 + 3 * ((size_t)n + MAX_SPLIT_WG)) * sizeof(int));
+    }
+    L.bar = off; off += align_up((size_t)2 * n * sizeof(unsigned int));
     L.st = off; off += align_up(n * sizeof(BState));
     L.pop[0] = off; off += align_up(pe * 8);
     L.pop[1] = off; off += align_up(pe * 8);
@@ -549,6 +768,9 @@ struct lbw_batch {
     hipEvent_t ev[2];
     bool ev_recorded;
     int cfg;
+    int nwg;          // workgroups of the current configuration's launch
+    int plan_nwg[2];  // workgroups of the plans in the workspace (one per instance; split)
+    int plan1_cfg;    // configuration whose split plan is in the workspace (-1: none)
     bool initialized;
     long step;
     int cur;   // host mirror of every instance's population buffer parity
@@ -575,7 +797,10 @@ static BatchArgs batch_args(lbw_batch *b, int nsteps)
 {
     BatchArgs a{};
     a.inst = (const BInst *)(b->ws + b->L.inst);
-    a.order = (const int *)(b->ws + b->L.order);
+    const int k = CONFIGS[b->cfg].split;
+    a.woff = (const int *)(b->ws + b->L.plan[k]);
+    a.items = a.woff + b->plan_nwg[k] + 1;
+    a.bar = (unsigned int *)(b->ws + b->L.bar);
     a.pop0 = (double *)(b->ws + b->L.pop[0]);
     a.pop1 = (double *)(b->ws + b->L.pop[1]);
     a.ez = (double *)(b->ws + b->L.ez);
@@ -647,7 +872,11 @@ lbw_status lbw_batch_create(const lbw_instance_desc *d, int n, void *ws, size_t 
     b->stream = (hipStream_t)stream;
     b->capture_stream = nullptr;
     b->ev_recorded = false;
-    b->cfg = 4;  // 1024 threads, one node per thread
+    b->cfg = 4;  // 1024 threads, one node per thread, one workgroup per instance
+    b->nwg = n;
+    b->plan_nwg[0] = n;
+    b->plan_nwg[1] = 0;
+    b->plan1_cfg = -1;
     b->initialized = false;
     b->step = 0;
     b->cur = 0;
@@ -700,9 +929,13 @@ lbw_status lbw_batch_create(const lbw_instance_desc *d, int n, void *ws, size_t 
     chk(hipEventCreate(&b->ev[1]), "hipEventCreate");
     chk(hipMemcpyAsync(b->ws + L.inst, b->inst.data(), n * sizeof(BInst), hipMemcpyHostToDevice, b->stream),
         "hipMemcpyAsync");
-    chk(hipMemcpyAsync(b->ws + L.order, b->order.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream),
+    const Plan whole = plan_whole(b->order);
+    std::vector<int> buf(whole.woff);
+    buf.insert(buf.end(), whole.items.begin(), whole.items.end());
+    chk(hipMemcpyAsync(b->ws + L.plan[0], buf.data(), buf.size() * sizeof(int), hipMemcpyHostToDevice, b->stream),
         "hipMemcpyAsync");
     chk(hipMemsetAsync(b->ws + L.zeros, 0, 64, b->stream), "hipMemsetAsync");
+    chk(hipMemsetAsync(b->ws + L.bar, 0, (size_t)2 * n * sizeof(unsigned int), b->stream), "hipMemsetAsync");
     chk(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     if (rc != LBW_OK) {
         lbw_batch_destroy(b);
@@ -740,6 +973,7 @@ lbw_status lbw_batch_init(lbw_batch *b, const double *n_init)
     BHIPCHK(b, hipMemcpyAsync(b->ws + b->L.st, st.data(), n * sizeof(BState), hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipMemsetAsync(b->ws + b->L.ez, 0, b->L.fld_elems * 8, b->stream));
     BHIPCHK(b, hipMemsetAsync(b->ws + b->L.lag, 0, b->L.lag_elems * 8 + 8, b->stream));
+    BHIPCHK(b, hipMemsetAsync(b->ws + b->L.bar, 0, (size_t)2 * n * sizeof(unsigned int), b->stream));
     size_t off = 0;
     std::vector<double> A;
     for (int i = 0; i < n; ++i) {
@@ -796,9 +1030,9 @@ lbw_status lbw_batch_init(lbw_batch *b, const double *n_init)
 static lbw_status launch_step(lbw_batch *b, int nsteps, int use_graph)
 {
     const BatchArgs a = batch_args(b, nsteps);
-    const int nblocks = (int)b->inst.size();
+    const int nblocks = b->nwg;
     if (!use_graph) {
-        launch_config(b->cfg, a, nblocks, b->stream);
+        BHIPCHK(b, launch_config(b->cfg, a, nblocks, b->stream));
         BHIPCHK(b, hipGetLastError());
         return LBW_OK;
     }
@@ -809,9 +1043,9 @@ static lbw_status launch_step(lbw_batch *b, int nsteps, int use_graph)
         if (!b->capture_stream) BHIPCHK(b, hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
         BHIPCHK(b, hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
-        launch_config(b->cfg, a, nblocks, b->capture_stream);
-        const hipError_t le = hipGetLastError();
+        const hipError_t le = launch_config(b->cfg, a, nblocks, b->capture_stream);
         const hipError_t ce = hipStreamEndCapture(b->capture_stream, &g);
+        (void)hipGetLastError();
         BHIPCHK(b, le);
         BHIPCHK(b, ce);
         b->graph_defs.push_back(g);
@@ -858,15 +1092,78 @@ lbw_status lbw_batch_get_timing(lbw_batch *b, double *ms)
     return LBW_OK;
 }
 
+// Make configuration ci current: for the split schedule, check that enough
+// workgroups can be resident, plan the work lists and upload them (graphs
+// captured for another split configuration then go: they read the lists).
+static lbw_status apply_config(lbw_batch *b, int ci)
+{
+    const int n = (int)b->inst.size();
+    if (!CONFIGS[ci].split) {
+        b->cfg = ci;
+        b->nwg = n;
+        return LBW_OK;
+    }
+    if (b->plan1_cfg != ci) {
+        const int resident = std::min(resident_workgroups(ci), MAX_SPLIT_WG);
+        if (resident < n)
+            return bfail(b, LBW_ERR_UNSUPPORTED,
+                         "split schedule: fewer co-resident workgroups than instances, or no cooperative launch");
+        const Plan p = plan_split(b->d, b->order, deep_width(CONFIGS[ci]), resident);
+        std::vector<int> buf(p.woff);
+        buf.insert(buf.end(), p.items.begin(), p.items.end());
+        BHIPCHK(b, hipStreamSynchronize(b->stream));  // no launch still reads the old lists
+        BHIPCHK(b, hipMemcpyAsync(b->ws + b->L.plan[1], buf.data(), buf.size() * sizeof(int), hipMemcpyHostToDevice,
+                                  b->stream));
+        BHIPCHK(b, hipStreamSynchronize(b->stream));  // the host buffer goes out of scope
+        for (auto it = b->graphs.begin(); it != b->graphs.end();) {
+            if (CONFIGS[it->first.second].split) {
+                (void)hipGraphExecDestroy(it->second);
+                it = b->graphs.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        b->plan_nwg[1] = (int)p.woff.size() - 1;
+        b->plan1_cfg = ci;
+    }
+    b->cfg = ci;
+    b->nwg = b->plan_nwg[1];
+    return LBW_OK;
+}
+
+static int find_config(int threads, int cpt, int split)
+{
+    for (int i = 0; i < NCONFIG; ++i)
+        if (CONFIGS[i].threads == threads && CONFIGS[i].cpt == cpt && CONFIGS[i].split == split) return i;
+    return -1;
+}
+
 lbw_status lbw_batch_set_config(lbw_batch *b, int threads, int cpt)
 {
     if (!b) return LBW_ERR_ARG;
-    for (int i = 0; i < NCONFIG; ++i)
-        if (CONFIGS[i].threads == threads && CONFIGS[i].cpt == cpt) {
-            b->cfg = i;
-            return LBW_OK;
-        }
-    return bfail(b, LBW_ERR_ARG, "configuration must be 256 or 512 threads with 1 or 2 nodes each, or 1024 threads with 1");
+    const int ci = find_config(threads, cpt, 0);
+    if (ci < 0)
+        return bfail(b, LBW_ERR_ARG,
+                     "configuration must be 256 or 512 threads with 1 or 2 nodes each, or 1024 threads with 1");
+    return apply_config(b, ci);
+}
+
+lbw_status lbw_batch_set_schedule(lbw_batch *b, int threads, int cpt, int split)
+{
+    if (!b) return LBW_ERR_ARG;
+    const int ci = find_config(threads, cpt, split ? 1 : 0);
+    if (ci < 0) return bfail(b, LBW_ERR_ARG, "no such launch configuration");
+    return apply_config(b, ci);
+}
+
+lbw_status lbw_batch_get_schedule(const lbw_batch *b, int *threads, int *cpt, int *split, int *workgroups)
+{
+    if (!b || !threads || !cpt || !split || !workgroups) return LBW_ERR_ARG;
+    *threads = CONFIGS[b->cfg].threads;
+    *cpt = CONFIGS[b->cfg].cpt;
+    *split = CONFIGS[b->cfg].split;
+    *workgroups = b->nwg;
+    return LBW_OK;
 }
 
 lbw_status lbw_batch_get_config(const lbw_batch *b, int *threads, int *cpt)
@@ -906,7 +1203,10 @@ lbw_status lbw_batch_autotune(lbw_batch *b, int probe_steps, int *threads, int *
     double best = 1e300;
     int best_i = b->cfg;
     for (int i = 0; i < NCONFIG; ++i) {
-        b->cfg = i;
+        if (apply_config(b, i) != LBW_OK) {  // a split schedule the device cannot hold
+            rc = LBW_OK;
+            continue;
+        }
         // one untimed launch (first use of this kernel), then the timed one
         for (int rep = 0; rep < 2; ++rep) {
             rc = snapshot(b, false);
@@ -930,7 +1230,8 @@ lbw_status lbw_batch_autotune(lbw_batch *b, int probe_steps, int *threads, int *
     lbw_status rc2 = snapshot(b, false);
     if (rc == LBW_OK) rc = rc2;
     BHIPCHK(b, hipStreamSynchronize(b->stream));
-    b->cfg = best_i;
+    rc2 = apply_config(b, best_i);
+    if (rc == LBW_OK) rc = rc2;
     if (threads) *threads = CONFIGS[best_i].threads;
     if (cpt) *cpt = CONFIGS[best_i].cpt;
     return rc;

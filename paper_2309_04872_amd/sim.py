@@ -89,10 +89,11 @@ class Sim:
             self._lib.lbw_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # during interpreter shutdown the HIP runtime (or a profiler's hooks
         # around it) may already be gone: leave the handle to the process exit
-        if sys.is_finalizing():
+        # (module globals such as sys may be None by then, hence the default)
+        if _finalizing():
             return
         try:
             self.close()

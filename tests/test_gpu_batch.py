@@ -13,6 +13,7 @@ LP = 2 * np.pi  # plasma wavelength in units of c / omega_p
 CL = {"lec": oracle.LEC, "warmc": oracle.WARMC}
 BC = {"open": oracle.OPEN, "periodic": oracle.PERIODIC}
 CONFIGS = [(256, 1), (256, 2), (512, 1), (512, 2), (1024, 1)]
+SPLIT_CONFIGS = [(256, 2), (512, 1), (512, 2), (1024, 1)]
 
 
 def _mixed_instances():
@@ -122,6 +123,7 @@ def test_batch_full_scan_sampled():
     cfg = b.autotune(probe_steps=10)
     print("autotuned", cfg, flush=True)
     assert cfg in CONFIGS
+    print("schedule", b.schedule(), flush=True)
     b.step(steps, graph=True)
     bad = b.nonfinite()
     nz = np.array([d["nz"] for d in insts])
@@ -190,17 +192,24 @@ def test_batch_autotune_restores_state():
         assert np.array_equal(x, y)
 
 
-def test_batch_nonfinite_flags():
+@pytest.mark.parametrize("split", [False, True])
+def test_batch_nonfinite_flags(split):
     """An instance whose pressure term overflows (n = 1e200: n0^3 is not
     representable) turns non-finite and is counted; the other instances
-    are unaffected."""
-    insts = [dict(nz=300, closure="lec", mu=1e-3, alpha=0.2, sigma_z=0.5),
-             dict(nz=260, closure="lec", mu=1e-3, alpha=0.0),
-             dict(nz=310, closure="warmc", mu=1e-3, alpha=0.2, sigma_z=0.5)]
-    dens = [np.ones(300), np.full(260, 1e200), np.ones(310)]
-    b = _batch(insts, dens).step(5)
+    are unaffected. Under the split schedule the count is summed over the
+    instance's workgroups."""
+    k = 10 if split else 1  # long enough to be shared by several workgroups
+    insts = [dict(nz=300 * k, closure="lec", mu=1e-3, alpha=0.2, sigma_z=0.5),
+             dict(nz=260 * k, closure="lec", mu=1e-3, alpha=0.0),
+             dict(nz=310 * k, closure="warmc", mu=1e-3, alpha=0.2, sigma_z=0.5)]
+    dens = [np.ones(300 * k), np.full(260 * k, 1e200), np.ones(310 * k)]
+    b = _batch(insts, dens)
+    if split:
+        b.set_schedule(256, 2, split=True)
+        assert b.schedule()[3] > len(insts)
+    b.step(5)
     bad = b.nonfinite()
-    assert bad[0] == 0 and bad[2] == 0 and bad[1] == 260, bad
+    assert bad[0] == 0 and bad[2] == 0 and bad[1] == 260 * k, bad
     ref = _batch([insts[0], insts[2]], [dens[0], dens[2]]).step(5)
     assert np.array_equal(b.read(0, "n"), ref.read(0, "n"))
     assert np.array_equal(b.read(2, "ez"), ref.read(1, "ez"))
@@ -223,3 +232,62 @@ def test_batch_errors():
         b.init([np.ones(300), -np.ones(513)])
     with pytest.raises(LbwError, match="UNSTABLE"):
         Batch([dict(nz=64, closure="lec", mu=1e-3, tau_tilde=0.5)])
+
+
+# ---------------------------------------------------------------------------
+# Split schedule: long instances shared by several co-resident workgroups
+# (cooperative launch), short ones packed into one workgroup's list.
+
+@pytest.mark.parametrize("cfg", SPLIT_CONFIGS)
+def test_batch_split_schedule_bitwise(cfg):
+    """Every node runs the same arithmetic under every schedule, so the split
+    schedule's results are the bits of one workgroup per instance, through
+    single steps, pairs, deep passes and a second call."""
+    insts = _mixed_instances()
+    dens = _densities(insts, seed=17)
+    ref = _batch(insts, dens)
+    ref.set_config(*cfg)
+    ref.step(120).step(81)
+    b = _batch(insts, dens)
+    b.set_schedule(*cfg, split=True)
+    t, c, split, wg = b.schedule()
+    print("split schedule", cfg, "workgroups", wg, flush=True)
+    assert (t, c) == cfg and split and wg > len(insts)
+    b.step(120).step(81)
+    assert b.step_count == 201
+    for x, y in zip(_snapshot(ref, ("n", "uz", "ez", "thzz", "lambda")), _snapshot(b, ("n", "uz", "ez", "thzz", "lambda"))):
+        assert np.array_equal(x, y)
+    assert np.array_equal(ref.nonfinite(), b.nonfinite())
+
+
+def test_batch_split_graph_replay():
+    """The split schedule captured in a HIP graph and replayed, with eager
+    work between the replays, equals eager launches bit for bit."""
+    insts = _mixed_instances()
+    dens = _densities(insts, seed=19)
+    a = _batch(insts, dens)
+    g = _batch(insts, dens)
+    for x in (a, g):
+        x.set_schedule(1024, 1, split=True)
+    for _ in range(3):
+        a.step(40)
+        g.step(40, graph=True)
+        for x, y in zip(_snapshot(a), _snapshot(g)):
+            assert np.array_equal(x, y)
+
+
+def test_batch_split_full_scan_matches_whole():
+    """The 256-instance scan, 200 steps: the split schedule (the longest
+    instances shared, the short ones packed) against one workgroup per
+    instance, bit for bit on every instance."""
+    from paper_2309_04872_amd import workloads
+
+    insts = workloads.batch_instances()
+    ref = _batch(insts).step(200)
+    b = _batch(insts)
+    b.set_schedule(1024, 1, split=True)
+    print("scan split schedule", b.schedule(), flush=True)
+    b.step(200)
+    for i in range(len(insts)):
+        for q in ("n", "uz", "ez"):
+            assert np.array_equal(ref.read(i, q), b.read(i, q)), (i, q)
