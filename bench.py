@@ -259,7 +259,7 @@ def batch_bytes_per_step(insts):
     return sum(d["nz"] * bytes_per_lu(1, d["closure"], "fp64") for d in insts)
 
 
-BATCH_TRAFFIC_PER_STEP = None  # re-measured after the kernel's arguments changed (profiles/k_batch1d_batch1d_scan.md)
+BATCH_TRAFFIC_PER_STEP = 33.52e6  # profiles/k_batch1d_batch1d_scan.md
 BATCH_PASS_DEPTH = 16
 
 
