@@ -63,10 +63,10 @@ TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake2d_lec_fp32", "fp32"): 301.1e6,
     ("wake2d_lec_fp32", "fp64"): 605.2e6,
     ("wake2d_warmc", "fp64"): 6710.4e6,
-    ("wake2d_warmc", "fp32"): 3956.0e6,
-    ("wake2d_warmc", "fp16dev"): 2119.7e6,
+    ("wake2d_warmc", "fp32"): 3760.1e6,
+    ("wake2d_warmc", "fp16dev"): 2080.9e6,
     ("wake_axi_lec", "fp64"): 1092.0e6,
-    ("wake_axi_lec", "fp32"): 544.2e6,
+    ("wake_axi_lec", "fp32"): 546.6e6,
     ("wake_axi_warmc", "fp64"): 3071.8e6,
     ("wake_axi_warmc", "fp32"): 1600.6e6,
     ("wake2d_lec_fp32", "fp16dev"): 170.5e6,
@@ -93,22 +93,32 @@ def cpu_model():
 
 
 def copy_bandwidth_gbs(stream, nbytes=1 << 30, reps=10):
-    """Device-to-device copy bandwidth (read + write bytes / time) of a plain
-    torch copy on the same GPU, HIP events on ``stream``."""
+    """Practical HBM ceiling: read + write bytes over the duration of the
+    library's streaming copy (lbw_stream_copy: one 16-byte non-temporal load
+    and store per thread) of nbytes, HIP events on ``stream``."""
+    import ctypes
+
     import torch
 
-    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    y = torch.empty_like(x)
+    from paper_2309_04872_amd import _lib
+
+    L = _lib.load()
     with torch.cuda.stream(stream):
-        y.copy_(x)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            y.copy_(x)
-        e1.record(stream)
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+    args = (ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(x.data_ptr()), nbytes, ctypes.c_void_p(stream.cuda_stream))
+    if L.lbw_stream_copy(*args) != 0:
+        raise RuntimeError("lbw_stream_copy failed")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        L.lbw_stream_copy(*args)
+    e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    if not torch.equal(x, y):
+        raise RuntimeError("lbw_stream_copy produced a wrong copy")
     del x, y
     return 2 * nbytes / (ms / 1e3) / 1e9
 

@@ -410,6 +410,17 @@ void lbw_batch_destroy(lbw_batch *b);
 const char *lbw_last_error(const lbw_sim *sim);
 const char *lbw_version(void);
 
+/* Measurement aid, not a step of the method: copies bytes bytes from src to
+ * dst (device pointers, 16-byte aligned, not overlapping; bytes a multiple
+ * of 16) on stream (a hipStream_t; NULL: the null stream) with a plain
+ * streaming kernel, one 16-byte non-temporal load and store per thread in
+ * 256-thread workgroups. Read plus write bytes over its duration is the HBM
+ * rate that a simple kernel sustains on the device, the practical ceiling
+ * beside the nominal peak. Asynchronous. LBW_ERR_ARG for a NULL pointer,
+ * misalignment, overlap or a size not a multiple of 16 (checked on the host,
+ * before any launch), LBW_ERR_HIP if the launch fails. */
+lbw_status lbw_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 /* Releases the handle; the workspace and stream stay the caller's. */
 void lbw_destroy(lbw_sim *sim);
 

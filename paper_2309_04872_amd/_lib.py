@@ -35,7 +35,7 @@ EXPORTS = [
     "lbw_batch_set_config", "lbw_batch_get_config", "lbw_batch_set_schedule", "lbw_batch_get_schedule",
     "lbw_batch_autotune", "lbw_batch_read",
     "lbw_batch_nonfinite", "lbw_batch_step_count", "lbw_batch_get_timing", "lbw_batch_last_error",
-    "lbw_batch_destroy",
+    "lbw_batch_destroy", "lbw_stream_copy",
 ]
 BATCH_EZ = 100
 
@@ -183,6 +183,8 @@ def load(path: str | None = None):
     L.lbw_batch_last_error.argtypes = [vp]
     L.lbw_batch_destroy.restype = None
     L.lbw_batch_destroy.argtypes = [vp]
+    L.lbw_stream_copy.restype = ctypes.c_int
+    L.lbw_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     if path is None:
         _LIB = L
     return L

@@ -61,23 +61,30 @@ template <int DIM, int CL> struct NScal {
 // state for FP32 and FP16 storage); CT is the arithmetic type of the collision.
 template <class ST> struct Store;
 // Loads and stores take a uniform plane pointer and a 32-bit node offset.
+// st_nt: the same store with the non-temporal hint (streamed past the caches).
 // rnd(v): the value a store of v followed by a load returns.
 template <> struct Store<double> {
     using ct = double;
     __device__ static double ld(const double *p, int i) { return p[i]; }
     __device__ static void st(double *p, int i, double v) { p[i] = v; }
+    __device__ static void st_nt(double *p, int i, double v) { __builtin_nontemporal_store(v, p + i); }
     __device__ static double rnd(double v) { return v; }
 };
 template <> struct Store<float> {
     using ct = float;
     __device__ static float ld(const float *p, int i) { return p[i]; }
     __device__ static void st(float *p, int i, float v) { p[i] = v; }
+    __device__ static void st_nt(float *p, int i, float v) { __builtin_nontemporal_store(v, p + i); }
     __device__ static float rnd(float v) { return v; }
 };
 template <> struct Store<__half> {
     using ct = float;
     __device__ static float ld(const __half *p, int i) { return __half2float(p[i]); }
     __device__ static void st(__half *p, int i, float v) { p[i] = __float2half_rn(v); }
+    __device__ static void st_nt(__half *p, int i, float v)
+    {
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), (unsigned short *)p + i);
+    }
     __device__ static float rnd(float v) { return __half2float(__float2half_rn(v)); }
 };
 

@@ -96,7 +96,8 @@ __device__ __forceinline__ void collide_all(CT (*s)[Lattice<DIM>::Q], const doub
 // STRIP > 1: inside an XCD's band the tiles run z-major through strips of
 // STRIP tile-rows, so that the rows a tile shares with the tiles above and
 // below are still in that XCD's L2 when they are read again.
-template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false, int STRIP = 1>
+// NTS: the post-collision populations are stored with the non-temporal hint.
+template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false, int STRIP = 1, bool NTS = false>
 __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 {
     using L = Lattice<2>;
@@ -445,8 +446,10 @@ __global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int q = 0; q < Q; ++q)
-                    Store<ST>::st(dst + (size_t)(k * Q + q) * nc, (int)c, s[r][k][q]);
+                for (int q = 0; q < Q; ++q) {
+                    if constexpr (NTS) Store<ST>::st_nt(dst + (size_t)(k * Q + q) * nc, (int)c, s[r][k][q]);
+                    else Store<ST>::st(dst + (size_t)(k * Q + q) * nc, (int)c, s[r][k][q]);
+                }
         }
     };
     if (edge)

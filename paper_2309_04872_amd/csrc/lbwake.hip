@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <type_traits>
@@ -247,13 +248,26 @@ void set_io(lbw_sim *s, StepArgs &a)
     a.by_out = (double *)(s->ws + s->L.fld[1 - s->fcur][2]);
 }
 
+// Non-temporal population stores in the 2D fused step, where they measured
+// faster (FP32 warm slab 4096 x 1024: 726 -> 693 us, FP16-deviation 513 ->
+// 493 us; FP32 local equilibrium 2048 x 512: 66.4 -> 64.9 us, axisymmetric
+// 3000 x 600: 156 -> 146 us). Elsewhere they measured slower (FP64 warm slab
+// 1254 -> 1350 us, FP16 local equilibrium 48.9 -> 56.0 us, warm
+// axisymmetric FP32 371 -> 377 us and FP16 284 -> 305 us).
+template <int CL, class ST, bool AXI> constexpr bool nt_pop_stores()
+{
+    if constexpr (std::is_same<ST, float>::value) return CL == LEC || !AXI;
+    else if constexpr (std::is_same<ST, __half>::value) return CL == WARMC && !AXI;
+    else return false;
+}
+
 template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
     template <class T> static void launch2d(const StepArgs &a, hipStream_t st)
     {
         // one-dimensional grid: the kernel maps blocks to tiles XCD by XCD
         dim3 grid(((a.nz + T::TZ - 1) / T::TZ) * ((a.nx + T::TX - 1) / T::TX));
-        hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP>), grid,
-                           dim3(T::TZ * T::TX / T::CPT), 0, st, a);
+        hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP, nt_pop_stores<CL, ST, AXI>()>),
+                           grid, dim3(T::TZ * T::TX / T::CPT), 0, st, a);
     }
     static void step(const StepArgs &a, hipStream_t st)
     {
@@ -466,6 +480,33 @@ size_t lbw_workspace_bytes(const lbw_grid_desc *grid)
 }
 
 const char *lbw_version(void) { return "lbwake 0.1 (gfx950)"; }
+
+// Streaming-copy reference: one 16-byte non-temporal load and store per thread.
+// (A sweep of 1, 2, 4 and 8 accesses per thread and 256- to 1024-thread
+// workgroups, with and without the non-temporal hint, found this form the
+// fastest on gfx950.)
+typedef unsigned int lbw_v4u __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(const lbw_v4u *__restrict__ src, lbw_v4u *__restrict__ dst,
+                                                     size_t n16)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+lbw_status lbw_stream_copy(void *dst, const void *src, size_t bytes, void *stream)
+{
+    if (!dst || !src) return LBW_ERR_ARG;
+    const uintptr_t d = (uintptr_t)dst, sp = (uintptr_t)src;
+    if ((d | sp | bytes) & 15) return LBW_ERR_ARG;
+    if (d < sp + bytes && sp < d + bytes) return LBW_ERR_ARG;
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return LBW_OK;
+    const size_t blocks = (n16 + 255) / 256;
+    if (blocks > 0xFFFFFFFFull) return LBW_ERR_ARG;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const lbw_v4u *)src, (lbw_v4u *)dst, n16);
+    return hipGetLastError() == hipSuccess ? LBW_OK : LBW_ERR_HIP;
+}
 
 lbw_status lbw_create(const lbw_grid_desc *grid, void *ws, size_t ws_bytes, void *stream,
                       lbw_sim **out)

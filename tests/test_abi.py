@@ -160,3 +160,19 @@ def test_batch_create_validation(lib):
     assert create(_insts(_inst()), 1, ws=256 * 1024 + 8) == -2      # misaligned
     assert create(_insts(_inst()), 1, nbytes=64) == -2              # too small
     assert create(_insts(_inst()), 0, nbytes=1 << 20) == -1
+
+
+def test_stream_copy_host_checks(lib):
+    """lbw_stream_copy refuses, on the host and before any launch, NULL
+    pointers, misalignment, overlap and sizes not a multiple of 16; an empty
+    copy launches nothing."""
+    vp = ctypes.c_void_p
+    a, b = 1 << 20, 1 << 24  # addresses only; never dereferenced on these paths
+    assert lib.lbw_stream_copy(None, vp(a), 16, None) == -1
+    assert lib.lbw_stream_copy(vp(b), None, 16, None) == -1
+    assert lib.lbw_stream_copy(vp(b + 8), vp(a), 16, None) == -1
+    assert lib.lbw_stream_copy(vp(b), vp(a + 4), 16, None) == -1
+    assert lib.lbw_stream_copy(vp(b), vp(a), 24, None) == -1
+    assert lib.lbw_stream_copy(vp(a + 16), vp(a), 64, None) == -1  # overlap
+    assert lib.lbw_stream_copy(vp(a), vp(a + 16), 64, None) == -1
+    assert lib.lbw_stream_copy(vp(b), vp(a), 0, None) == 0

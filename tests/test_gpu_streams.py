@@ -61,3 +61,28 @@ def test_batch_on_side_stream_bitwise():
             np.testing.assert_array_equal(b.read(i, q), ref.read(i, q))
     b.close()
     ref.close()
+
+
+@pytest.mark.gpu
+def test_stream_copy_exact():
+    """The streaming-copy reference copies bit for bit, a ragged size (not a
+    multiple of the workgroup's 4096 bytes) on a side stream."""
+    import ctypes
+
+    import torch
+
+    from paper_2309_04872_amd import _lib
+
+    L = _lib.load()
+    st = torch.cuda.Stream()
+    n = 16 * 1000003
+    g = torch.Generator(device="cpu").manual_seed(7)
+    x = torch.randint(0, 256, (n,), dtype=torch.uint8, generator=g).cuda()
+    y = torch.zeros(n + 64, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    rc = L.lbw_stream_copy(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(x.data_ptr()), n,
+                           ctypes.c_void_p(st.cuda_stream))
+    assert rc == 0
+    st.synchronize()
+    assert torch.equal(y[:n], x)
+    assert int(y[n:].count_nonzero()) == 0
