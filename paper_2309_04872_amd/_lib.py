@@ -89,6 +89,11 @@ def load(path: str | None = None):
     if not os.path.exists(p):
         raise LibraryMissing(
             f"{p} is missing: build the HIP library first (python -m paper_2309_04872_amd.build)")
+    # torch (and the HIP runtime it brings) before the library: a process
+    # that loaded the library first and torch afterwards found no GPU at the
+    # library's first HIP call
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(p)
     vp = ctypes.c_void_p
     L.lbw_workspace_bytes.restype = ctypes.c_size_t

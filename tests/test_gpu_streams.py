@@ -86,3 +86,22 @@ def test_stream_copy_exact():
     st.synchronize()
     assert torch.equal(y[:n], x)
     assert int(y[n:].count_nonzero()) == 0
+
+
+@pytest.mark.gpu
+def test_library_loaded_before_torch():
+    """A fresh process that loads the library through the binding before it
+    imports torch itself still finds the GPU."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2309_04872_amd import _lib\n"
+            "L = _lib.load()\n"
+            "from paper_2309_04872_amd.sim import Sim\n"
+            "s = Sim(2, 64, 16, closure='lec', storage='fp32')\n"
+            "s.init_plasma(1e-2); s.step(3); s.close()\n"
+            "print('ok')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
