@@ -250,10 +250,13 @@ void set_io(lbw_sim *s, StepArgs &a)
 
 // Non-temporal population stores in the 2D fused step, where they measured
 // faster (FP32 warm slab 4096 x 1024: 726 -> 693 us, FP16-deviation 513 ->
-// 493 us; FP32 local equilibrium 2048 x 512: 66.4 -> 64.9 us, axisymmetric
-// 3000 x 600: 156 -> 146 us). Elsewhere they measured slower (FP64 warm slab
-// 1254 -> 1350 us, FP16 local equilibrium 48.9 -> 56.0 us, warm
-// axisymmetric FP32 371 -> 377 us and FP16 284 -> 305 us).
+// 493 us; FP32 local equilibrium axisymmetric 3000 x 600: 156 -> 146 us).
+// Elsewhere they measured slower (FP64 warm slab 1254 -> 1350 us, FP16 local
+// equilibrium 48.9 -> 56.0 us, warm axisymmetric FP32 371 -> 377 us and FP16
+// 284 -> 305 us). Only when the two population buffers exceed the
+// last-level cache: below it the hint sends to HBM what the next kernel would
+// have read from that cache (1024 x 256 FP32 local equilibrium: the
+// canonicalisation after a step 15.6 -> 21.8 us).
 template <int CL, class ST, bool AXI> constexpr bool nt_pop_stores()
 {
     if constexpr (std::is_same<ST, float>::value) return CL == LEC || !AXI;
@@ -266,8 +269,17 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
     {
         // one-dimensional grid: the kernel maps blocks to tiles XCD by XCD
         dim3 grid(((a.nz + T::TZ - 1) / T::TZ) * ((a.nx + T::TX - 1) / T::TX));
-        hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP, nt_pop_stores<CL, ST, AXI>()>),
-                           grid, dim3(T::TZ * T::TX / T::CPT), 0, st, a);
+        constexpr int K = NScal<2, CL>::K;
+        const size_t pop_bytes = (size_t)a.ncell * 2 * K * 9 * sizeof(ST);
+        if constexpr (nt_pop_stores<CL, ST, AXI>()) {
+            if (pop_bytes > MALL_BYTES) {
+                hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP, true>), grid,
+                                   dim3(T::TZ * T::TX / T::CPT), 0, st, a);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP, false>), grid,
+                           dim3(T::TZ * T::TX / T::CPT), 0, st, a);
     }
     static void step(const StepArgs &a, hipStream_t st)
     {
