@@ -193,6 +193,22 @@ lbw_status lbw_step(lbw_sim *sim, int nsteps);
  * tau~ > 1/2 (Sec. 2.2, eq. diff-coeff); the check catches the rest. */
 lbw_status lbw_set_nonfinite_check(lbw_sim *sim, int every);
 
+/* Diagnostics every M steps (the reductions of lbw_diagnostics: FP64
+ * wavefront and workgroup sums, Sec. 2.2 moments and the Sec. 5 fields):
+ * with every = M > 0, lbw_step also ends its chunks on multiples of M steps
+ * (counted from lbw_init_plasma) and after each writes the 8 values of
+ * lbw_diagnostics for that step into the next row of device_series
+ * (caller-owned device memory, capacity rows of 8 doubles), asynchronously
+ * on the simulation's stream, without copies to the host or
+ * synchronisation. Rows beyond capacity are counted but not written;
+ * lbw_diagnostics_rows tells how many rows were due since the call.
+ * every = 0 turns recording off (the default). Results of the steps are the
+ * same bits as without recording. The buffer must stay valid while
+ * recording is on. LBW_ERR_ARG for negative arguments or for every > 0
+ * without a buffer of at least one row. */
+lbw_status lbw_set_diagnostics_every(lbw_sim *sim, int every, double *device_series, long capacity);
+long lbw_diagnostics_rows(const lbw_sim *sim);
+
 /* Recover one fluid observable at every node into host_out (count =
  * nx*nz doubles); synchronises the stream. The observables come from the
  * zeroth moments of the canonical populations (eq. disc-moments-ade) by the

@@ -26,7 +26,7 @@ FIELDS = {"ez": 0, "ex": 1, "by": 2, "wake_x": 3}
 # Every symbol include/lbwake.h declares.
 EXPORTS = [
     "lbw_workspace_bytes", "lbw_create", "lbw_init_plasma", "lbw_init_moments", "lbw_init_driver",
-    "lbw_set_field", "lbw_step", "lbw_set_nonfinite_check", "lbw_read_moment", "lbw_read_moment_device", "lbw_read_field",
+    "lbw_set_field", "lbw_step", "lbw_set_nonfinite_check", "lbw_set_diagnostics_every", "lbw_diagnostics_rows", "lbw_read_moment", "lbw_read_moment_device", "lbw_read_field",
     "lbw_diagnostics", "lbw_diagnostics_static", "lbw_step_count", "lbw_set_timing", "lbw_get_timing", "lbw_state_bytes", "lbw_save_state", "lbw_load_state",
     "lbw_last_error", "lbw_version", "lbw_destroy",
     "lbw_state_device_bytes", "lbw_save_state_device", "lbw_load_state_device", "lbw_step_record",
@@ -112,6 +112,10 @@ def load(path: str | None = None):
     L.lbw_step.argtypes = [vp, ctypes.c_int]
     L.lbw_set_nonfinite_check.restype = ctypes.c_int
     L.lbw_set_nonfinite_check.argtypes = [vp, ctypes.c_int]
+    L.lbw_set_diagnostics_every.restype = ctypes.c_int
+    L.lbw_set_diagnostics_every.argtypes = [vp, ctypes.c_int, vp, ctypes.c_long]
+    L.lbw_diagnostics_rows.restype = ctypes.c_long
+    L.lbw_diagnostics_rows.argtypes = [vp]
     L.lbw_read_moment.restype = ctypes.c_int
     L.lbw_read_moment.argtypes = [vp, ctypes.c_int, _dp, ctypes.c_size_t]
     L.lbw_read_moment_device.restype = ctypes.c_int

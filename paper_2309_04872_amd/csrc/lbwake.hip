@@ -187,6 +187,9 @@ struct lbw_sim {
     int persist;  // 1D: workgroups of the persistent kernel (-1: not queried yet, 0: unavailable)
     int lcur;     // 1D warm closure: the lagged values are in L.lag_alt (1) or L.lag (0)
     int check_every;  // non-finite check after every this many steps (0: off)
+    int diag_every;   // diagnostics recorded after every this many steps (0: off)
+    double *diag_series;  // caller's device rows of 8 values
+    long diag_capacity, diag_rows;  // rows the buffer holds, rows due so far
 };
 
 static char *lag_cur(lbw_sim *s) { return s->ws + (s->lcur ? s->L.lag_alt : s->L.lag); }
@@ -550,6 +553,9 @@ lbw_status lbw_create(const lbw_grid_desc *grid, void *ws, size_t ws_bytes, void
     s->persist = -1;
     s->lcur = 0;
     s->check_every = 0;
+    s->diag_every = 0;
+    s->diag_series = nullptr;
+    s->diag_capacity = s->diag_rows = 0;
     *out = s;
     return LBW_OK;
 }
@@ -853,23 +859,47 @@ static lbw_status step_chunk(lbw_sim *s, int nsteps, bool check)
     return LBW_OK;
 }
 
+// The diagnostics of the canonical state into the next row of the caller's
+// series (asynchronous; rows beyond its capacity are counted, not written).
+static lbw_status record_diagnostics(lbw_sim *s)
+{
+    const long row = s->diag_rows++;
+    if (row >= s->diag_capacity) return LBW_OK;
+    StepArgs a = base_args(s);
+    set_io(s, a);
+    double *part = (double *)(s->ws + s->L.part);
+    double *raw = (double *)(s->ws + s->L.diag);
+    ops_for(s->g).diag(a, part, s->L.nblk_diag, raw, s->stream);
+    hipLaunchKernelGGL(k_diag_publish, dim3(1), dim3(64), 0, s->stream, (const double *)raw,
+                       (const unsigned int *)(s->ws + s->L.fallbacks), (double)s->g.nz * s->g.nx, s->step,
+                       s->diag_series + 8 * row);
+    HIPCHK(s, hipGetLastError());
+    return LBW_OK;
+}
+
 lbw_status lbw_step(lbw_sim *s, int nsteps)
 {
     if (!s) return LBW_ERR_ARG;
     if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
     if (nsteps < 0) return fail(s, LBW_ERR_ARG, "nsteps must be >= 0");
     if (nsteps == 0) return LBW_OK;
-    if (s->check_every <= 0) return step_chunk(s, nsteps, false);
-    // chunks that end on multiples of check_every steps; the state after each
-    // is checked, and split calls equal one long call bit for bit
+    const long ce = s->check_every, de = s->diag_every;
+    if (ce <= 0 && de <= 0) return step_chunk(s, nsteps, false);
+    // chunks that end on multiples of check_every and of diag_every steps;
+    // split calls equal one long call bit for bit
     int left = nsteps;
     while (left > 0) {
-        const long to_check = s->check_every - s->step % s->check_every;
-        const int n = (int)std::min<long>(left, to_check);
-        const bool check = n == to_check;
-        lbw_status st = step_chunk(s, n, check);
+        long n = left;
+        if (ce > 0) n = std::min<long>(n, ce - s->step % ce);
+        if (de > 0) n = std::min<long>(n, de - s->step % de);
+        const bool check = ce > 0 && (s->step + n) % ce == 0;
+        lbw_status st = step_chunk(s, (int)n, check);
         if (st != LBW_OK) return st;
-        left -= n;
+        left -= (int)n;
+        if (de > 0 && s->step % de == 0) {
+            st = record_diagnostics(s);
+            if (st != LBW_OK) return st;
+        }
         if (check) {
             unsigned int flag = 0;
             HIPCHK(s, hipMemcpyAsync(&flag, s->ws + s->L.nonfinite, sizeof(flag), hipMemcpyDeviceToHost, s->stream));
@@ -881,6 +911,21 @@ lbw_status lbw_step(lbw_sim *s, int nsteps)
     }
     return LBW_OK;
 }
+
+lbw_status lbw_set_diagnostics_every(lbw_sim *s, int every, double *device_series, long capacity)
+{
+    if (!s) return LBW_ERR_ARG;
+    if (every < 0 || capacity < 0) return fail(s, LBW_ERR_ARG, "every and capacity must be >= 0");
+    if (every > 0 && (!device_series || capacity == 0))
+        return fail(s, LBW_ERR_ARG, "recording needs a device buffer of at least one row");
+    s->diag_every = every;
+    s->diag_series = every > 0 ? device_series : nullptr;
+    s->diag_capacity = every > 0 ? capacity : 0;
+    s->diag_rows = 0;
+    return LBW_OK;
+}
+
+long lbw_diagnostics_rows(const lbw_sim *s) { return s ? s->diag_rows : -1; }
 
 lbw_status lbw_set_nonfinite_check(lbw_sim *s, int every)
 {

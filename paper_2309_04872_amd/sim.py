@@ -155,6 +155,33 @@ class Sim:
         self._check(self._lib.lbw_set_nonfinite_check(self._h, int(every)))
         return self
 
+    def record_diagnostics(self, every, capacity=1024):
+        """Record the 8 values of diagnostics() after every ``every`` steps of
+        step() into a device tensor of ``capacity`` rows (every = 0: stop).
+        Asynchronous: nothing is copied to the host while stepping."""
+        import torch
+
+        ptr = None
+        if every > 0:
+            with torch.cuda.stream(self.stream):
+                self._diag_series = torch.full((capacity, 8), float("nan"), dtype=torch.float64,
+                                               device=self.device)
+            ptr = ctypes.c_void_p(self._diag_series.data_ptr())
+        self._check(self._lib.lbw_set_diagnostics_every(self._h, int(every), ptr,
+                                                        int(capacity) if every > 0 else 0))
+        return self
+
+    def diagnostics_series(self):
+        """The rows recorded since record_diagnostics() (numpy, rows x 8:
+        sum n, field energy, kinetic energy, Gauss residual, max lattice Mach,
+        non-finite nodes, recovery fallbacks, step); synchronises the stream."""
+        rows = int(self._lib.lbw_diagnostics_rows(self._h))
+        series = getattr(self, "_diag_series", None)
+        if series is None:
+            return np.zeros((0, 8))
+        self.stream.synchronize()
+        return series[:min(rows, series.shape[0])].cpu().numpy()
+
     @property
     def step_count(self):
         return int(self._lib.lbw_step_count(self._h))

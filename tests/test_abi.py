@@ -176,3 +176,8 @@ def test_stream_copy_host_checks(lib):
     assert lib.lbw_stream_copy(vp(a + 16), vp(a), 64, None) == -1  # overlap
     assert lib.lbw_stream_copy(vp(a), vp(a + 16), 64, None) == -1
     assert lib.lbw_stream_copy(vp(b), vp(a), 0, None) == 0
+
+
+def test_diagnostics_every_null_sim(lib):
+    assert lib.lbw_set_diagnostics_every(None, 10, None, 4) == -1
+    assert lib.lbw_diagnostics_rows(None) == -1

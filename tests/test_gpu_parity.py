@@ -674,3 +674,50 @@ def test_nonfinite_check_field_and_bits():
     with pytest.raises(LbwError) as e:
         s.step(25)
     assert e.value.code == -5 and s.step_count == 30
+
+
+@pytest.mark.parametrize("closure", ["lec", "warmc"])
+def test_diagnostics_every_m_steps(closure):
+    """Diagnostics recorded every 25 steps inside step() calls that do not end
+    on multiples of 25: each row equals diagnostics() of a second simulation
+    stopped at that step, bit for bit; a fourth row due beyond a capacity of
+    three is counted, not written; the state equals that of a third
+    simulation run without recording."""
+    nz, nx = 96, 40
+    d = 2 * np.pi / 32
+    kw = dict(delta=d, closure=closure, mu=0.02, n=workloads.density_noise((nx, nz), 1e-2, 5),
+              driver=dict(alpha=0.6, sigma_z=1.0, sigma_x=0.5, z0=4.0))
+    a, _ = make_pair(2, nz, nx, **kw)
+    b, _ = make_pair(2, nz, nx, **kw)
+    c, _ = make_pair(2, nz, nx, **kw)
+    a.record_diagnostics(25, capacity=3)
+    for n in (7, 60, 33):
+        a.step(n)
+    rows = a.diagnostics_series()
+    assert rows.shape == (3, 8) and a._lib.lbw_diagnostics_rows(a._h) == 4
+    for r, at in enumerate((25, 50, 75)):
+        b.step(at - b.step_count)
+        ref = b.diagnostics()
+        assert np.array_equal(rows[r], ref), (r, rows[r], ref)
+        assert rows[r][7] == at
+    c.step(100)
+    for q in ("n", "mz", "mx"):
+        assert np.array_equal(a.read(q), c.read(q))
+    assert np.array_equal(a.field("ez"), c.field("ez"))
+    a.record_diagnostics(0)
+    a.step(30)
+    assert a._lib.lbw_diagnostics_rows(a._h) == 0
+    for s in (a, b, c):
+        s.close()
+
+
+def test_diagnostics_every_argument_checks():
+    from paper_2309_04872_amd.sim import Sim
+
+    s = Sim(2, 32, 8, closure="lec")
+    s.init_plasma(0.01)
+    L = s._lib
+    assert L.lbw_set_diagnostics_every(s._h, -1, None, 0) == -1
+    assert L.lbw_set_diagnostics_every(s._h, 5, None, 4) == -1
+    assert L.lbw_set_diagnostics_every(s._h, 0, None, 0) == 0
+    s.close()
