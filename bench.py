@@ -60,18 +60,18 @@ def bytes_per_lu(dims, closure, storage):
 # 5.4 GB in FP64) the bytes are HBM bytes up to the re-reads that hit the
 # MALL. Valid for the kernel as profiled; remove an entry when it changes.
 TRAFFIC_BYTES_PER_LAUNCH = {
-    ("wake2d_lec_fp32", "fp32"): 301.1e6,
-    ("wake2d_lec_fp32", "fp64"): 605.2e6,
+    ("wake2d_lec_fp32", "fp32"): 301.2e6,
+    ("wake2d_lec_fp32", "fp64"): 605.3e6,
     ("wake2d_warmc", "fp64"): 6710.4e6,
-    ("wake2d_warmc", "fp32"): 3760.1e6,
-    ("wake2d_warmc", "fp16dev"): 2080.9e6,
+    ("wake2d_warmc", "fp32"): 3760.9e6,
+    ("wake2d_warmc", "fp16dev"): 2081.2e6,
     ("wake_axi_lec", "fp64"): 1092.0e6,
-    ("wake_axi_lec", "fp32"): 546.6e6,
-    ("wake_axi_warmc", "fp64"): 3071.8e6,
-    ("wake_axi_warmc", "fp32"): 1600.6e6,
-    ("wake2d_lec_fp32", "fp16dev"): 170.5e6,
-    ("wake_axi_lec", "fp16dev"): 307.6e6,
-    ("wake_axi_warmc", "fp16dev"): 892.7e6,
+    ("wake_axi_lec", "fp32"): 539.0e6,
+    ("wake_axi_warmc", "fp64"): 3072.7e6,
+    ("wake_axi_warmc", "fp32"): 1600.9e6,
+    ("wake2d_lec_fp32", "fp16dev"): 169.9e6,
+    ("wake_axi_lec", "fp16dev"): 307.8e6,
+    ("wake_axi_warmc", "fp16dev"): 892.3e6,
 }
 
 

@@ -28,7 +28,6 @@ struct StepArgs {
     double *lag;                 // warm closure lagged values, [NLAG][ncell], in place
     double *lag_alt;             // 1D warm closure: the other lagged-value buffer (multi-step passes)
     unsigned int *fallbacks;     // LEC recovery fallback counter
-    unsigned int *nonfinite;     // set by the finish kernels when a node is not finite (null: no check)
     const double *aref;          // per-scalar storage reference A_ref (device, K values)
     int nz, nx, ncell;
     int bcz, bcx;
@@ -38,6 +37,7 @@ struct StepArgs {
     int axi;                     // 2D: axisymmetric (z, r) geometry
     long step;
     Driver drv;
+    unsigned int *nonfinite;     // set by the finish kernels when a node is not finite (null: no check)
 };
 
 // Advected scalars that change sign under r -> -r in the axisymmetric
