@@ -291,6 +291,18 @@ lbw_status lbw_load_state_device(lbw_sim *sim, const void *device_src, long step
  * not included in lbw_set_timing's kernel timing. */
 lbw_status lbw_step_record(lbw_sim *sim, int nsteps, void *device_states, size_t stride);
 
+/* The same steps as lbw_step(sim, nsteps) from a canonical state at step n0,
+ * recording each fused launch's own output instead of a canonical state:
+ * record m (m = 0 .. nsteps - 1, at device_states + m * stride, same layout
+ * and stride rules) holds the post-collision populations f*^{n0+m} of step
+ * n0 + m (Sec. 2.2, before the streaming of Sec. 2.1) and the fields
+ * E^{n0+m}, B^{n0+m-1/2} of state n0 + m (its lagged-value part is not
+ * written). Each launch reads the previous record, and only the last is
+ * canonicalised, into the simulation, whose final state equals that of
+ * lbw_step(sim, nsteps) bit for bit. For the recompute of
+ * lbw_adjoint_step_post; asynchronous on the stream. */
+lbw_status lbw_step_record_post(lbw_sim *sim, int nsteps, void *device_states, size_t stride);
+
 /* ---------------------------------------------------------------------------
  * Discrete adjoint of the 2D local-equilibrium step (Sec. 2.2, Sec. 3.1,
  * Sec. 5): the transposed Jacobian of one step of lbw_step, and the
@@ -315,6 +327,15 @@ size_t lbw_adjoint_bytes(const lbw_sim *sim);
 size_t lbw_adjoint_workspace_bytes(const lbw_sim *sim);
 lbw_status lbw_adjoint_step(lbw_sim *sim, const void *state_n, const void *state_n1, long n, double *adj,
                             double *grad, void *scratch);
+/* lbw_adjoint_step for records of lbw_step_record_post: rec_n is the record
+ * of step n (post-collision f*^n, whose streaming gives state n+1's
+ * populations, and state n's fields); pops_n holds state n's populations,
+ * canonical (pops_n_post = 0, e.g. the checkpoint the records start from)
+ * or as the record of step n - 1 (pops_n_post = 1). The kernels stream
+ * those populations themselves while summing their moments; the result is
+ * bit for bit that of lbw_adjoint_step on the canonical states. */
+lbw_status lbw_adjoint_step_post(lbw_sim *sim, const void *pops_n, int pops_n_post, const void *rec_n, long n,
+                                 double *adj, double *grad, void *scratch);
 lbw_status lbw_adjoint_init_fields(lbw_sim *sim, const double *adj, double *grad, void *scratch);
 
 /* ---------------------------------------------------------------------------

@@ -30,6 +30,7 @@ EXPORTS = [
     "lbw_diagnostics", "lbw_diagnostics_static", "lbw_step_count", "lbw_set_timing", "lbw_get_timing", "lbw_state_bytes", "lbw_save_state", "lbw_load_state",
     "lbw_last_error", "lbw_version", "lbw_destroy",
     "lbw_state_device_bytes", "lbw_save_state_device", "lbw_load_state_device", "lbw_step_record",
+    "lbw_step_record_post", "lbw_adjoint_step_post",
     "lbw_adjoint_bytes", "lbw_adjoint_workspace_bytes", "lbw_adjoint_step", "lbw_adjoint_init_fields",
     "lbw_batch_workspace_bytes", "lbw_batch_create", "lbw_batch_init", "lbw_batch_step",
     "lbw_batch_set_config", "lbw_batch_get_config", "lbw_batch_set_schedule", "lbw_batch_get_schedule",
@@ -146,6 +147,10 @@ def load(path: str | None = None):
     L.lbw_destroy.argtypes = [vp]
     L.lbw_step_record.restype = ctypes.c_int
     L.lbw_step_record.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t]
+    L.lbw_step_record_post.restype = ctypes.c_int
+    L.lbw_step_record_post.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t]
+    L.lbw_adjoint_step_post.restype = ctypes.c_int
+    L.lbw_adjoint_step_post.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_long, vp, vp, vp]
     L.lbw_state_device_bytes.restype = ctypes.c_size_t
     L.lbw_state_device_bytes.argtypes = [vp]
     L.lbw_save_state_device.restype = ctypes.c_int

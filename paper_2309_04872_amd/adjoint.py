@@ -67,10 +67,16 @@ def last_timing():
     return dict(_TIMING)
 
 
-def loss_and_grad(cfg, weights, every=100, grad_out=1.0, timing=False):
+def loss_and_grad(cfg, weights, every=100, grad_out=1.0, timing=False, records="post"):
     """Loss and d loss / d weights (numpy), checkpoints every ``every`` steps.
     timing: record HIP events on the simulation's stream around the forward,
-    the recompute and the reverse steps (last_timing())."""
+    the recompute and the reverse steps (last_timing()). records: "post"
+    recomputes a segment recording each fused launch's output
+    (lbw_step_record_post, no per-step canonicalisation) for
+    lbw_adjoint_step_post; "canonical" records canonical states
+    (lbw_step_record) for lbw_adjoint_step. Both give the same bits."""
+    if records not in ("post", "canonical"):
+        raise ValueError("records must be 'post' or 'canonical'")
     import torch
 
     r = _Run(cfg, weights).start()
@@ -116,15 +122,25 @@ def loss_and_grad(cfg, weights, every=100, grad_out=1.0, timing=False):
         mark("rec0")
         with trace.marker("adjoint recompute"):
             sim.load_state_device(ckpt[n0], n0)
-            sim.save_state_device(buf[0:sb])
-            sim.step_record(n1 - n0, buf[sb:], sb)
+            if records == "post":
+                sim.step_record_post(n1 - n0, buf, sb)
+            else:
+                sim.save_state_device(buf[0:sb])
+                sim.step_record(n1 - n0, buf[sb:], sb)
         mark("rec1")
         mark("adj0")
         with trace.marker("adjoint reverse"):
             for n in range(n1 - 1, n0 - 1, -1):
                 m = n - n0
-                check(lib.lbw_adjoint_step(h, vp(buf[m * sb:].data_ptr()), vp(buf[(m + 1) * sb:].data_ptr()), n,
-                                           vp(adj.data_ptr()), vp(grad.data_ptr()), vp(scratch.data_ptr())))
+                if records == "post":
+                    # state n's populations: the checkpoint, or record m - 1 (post-collision)
+                    pops_n = ckpt[n0] if m == 0 else buf[(m - 1) * sb:]
+                    check(lib.lbw_adjoint_step_post(h, vp(pops_n.data_ptr()), int(m > 0),
+                                                    vp(buf[m * sb:].data_ptr()), n, vp(adj.data_ptr()),
+                                                    vp(grad.data_ptr()), vp(scratch.data_ptr())))
+                else:
+                    check(lib.lbw_adjoint_step(h, vp(buf[m * sb:].data_ptr()), vp(buf[(m + 1) * sb:].data_ptr()),
+                                               n, vp(adj.data_ptr()), vp(grad.data_ptr()), vp(scratch.data_ptr())))
         mark("adj1")
     check(lib.lbw_adjoint_init_fields(h, vp(adj.data_ptr()), vp(grad.data_ptr()), vp(scratch.data_ptr())))
     torch.cuda.synchronize(dev)

@@ -23,7 +23,8 @@
 namespace lbw {
 
 struct AdjArgs {
-    const void *fn, *fn1;                 // populations of the states at steps n and n+1
+    const void *fn, *fn1;                 // populations of the states at steps n and n+1 (canonical,
+                                          // or the post-collision values of the step before)
     const double *ez, *ex, *by;           // E^n, B^{n-1/2} (Yee arrays)
     double *lf, *lez, *lex, *lby;         // adjoint of the state, updated in place
     double *s_byt, *s_fs, *s_fz, *s_fx;   // scratch: adjoint of B', of f*, of F
@@ -153,6 +154,37 @@ __device__ __forceinline__ void moments3(const void *f, const AdjArgs &a, size_t
     }
 }
 
+// The same sums for populations held as the previous step's post-collision
+// values f*: node (j, i)'s population q is the one streamed from
+// (j - e_x, i - e_z) under the boundary rule (S7), as the canonicalisation
+// copies it; the same values in the same order, so the same bits.
+template <class ST>
+__device__ __forceinline__ void moments3_pulled(const void *f, const AdjArgs &a, int j, int i, double *A)
+{
+    using L = Lattice<2>;
+    const ST *src = (const ST *)f;
+    const size_t nc = (size_t)a.ncell;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < L::Q; ++q) {
+            const int c = fix_node(j - L::ex(q), a.nx, a.bcx) * a.nz + fix_node(i - L::ez(q), a.nz, a.bcz);
+            acc += (double)Store<ST>::ld(src + (size_t)(k * L::Q + q) * nc, c);
+        }
+        A[k] = a.aref[k] + acc;
+    }
+}
+
+// Moments of the state the pointer holds: canonical (PULLED = false) or the
+// post-collision populations of the step before (PULLED = true).
+template <class ST, bool PULLED>
+__device__ __forceinline__ void moments_of(const void *f, const AdjArgs &a, int j, int i, size_t c, double *A)
+{
+    if constexpr (PULLED) moments3_pulled<ST>(f, a, j, i, A);
+    else moments3<ST>(f, a, c, A);
+}
+
 // Forward node fields at node (j, i) from E^n and B^{n-1/2} (S3).
 struct NodeF {
     double ez, ex, by;
@@ -182,7 +214,8 @@ __device__ __forceinline__ NodeF node_fields_at(const AdjArgs &a, int j, int i)
 // (a) Reverse of S9 and S8 at every slot/node y: adjoint of B', the currents'
 // adjoint m'b, through the recovery at n+1 into the adjoint of A' (every
 // population of the node gets it; the stream gather adds it).
-template <class ST>
+// PULLED: fn1 holds the post-collision populations of step n (f*^n).
+template <class ST, bool PULLED>
 __global__ __launch_bounds__(256) void k_adj_maxwell(AdjArgs a)
 {
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
@@ -204,7 +237,7 @@ __global__ __launch_bounds__(256) void k_adj_maxwell(AdjArgs a)
     const double mxb = 0.5 * dt * (gather2(a.lex, jy, iy, 0, 0, false, false, nx, nz, bx, bz) +
                                    gather2(a.lex, jy, iy, 1, 0, false, false, nx, nz, bx, bz));
     double A[3];
-    moments3<ST>(a.fn1, a, y, A);
+    moments_of<ST, PULLED>(a.fn1, a, jy, iy, y, A);
     LecJ J;
     lec_jac(A[0], A[1], A[2], a, J);
     // m = n u: adjoint of u is n m_b, n gets m_b . u
@@ -254,7 +287,8 @@ __global__ __launch_bounds__(256) void k_adj_stream(AdjArgs a)
 // (c) Reverse of S6, S5, S2, S1 at node y: collision, forcing (the gradient
 // of phi gathers the forcing adjoint of the neighbours), recovery; writes
 // the adjoint of f^n and the node-field adjoints.
-template <class ST>
+// PULLED: fn holds the post-collision populations of step n - 1 (f*^{n-1}).
+template <class ST, bool PULLED>
 __global__ __launch_bounds__(256) void k_adj_collide(AdjArgs a)
 {
     using L = Lattice<2>;
@@ -264,7 +298,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(AdjArgs a)
     const int nz = a.nz, nx = a.nx, bz = a.bcz, bx = a.bcx;
     const size_t nc = (size_t)a.ncell;
     double A[3];
-    moments3<ST>(a.fn, a, y, A);
+    moments_of<ST, PULLED>(a.fn, a, jy, iy, y, A);
     LecJ J;
     lec_jac(A[0], A[1], A[2], a, J);
     const NodeF nf = node_fields_at(a, jy, iy);

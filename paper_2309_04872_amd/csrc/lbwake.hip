@@ -1242,6 +1242,62 @@ lbw_status lbw_step_record(lbw_sim *s, int nsteps, void *dev, size_t stride)
     return LBW_OK;
 }
 
+lbw_status lbw_step_record_post(lbw_sim *s, int nsteps, void *dev, size_t stride)
+{
+    if (!s || !dev) return fail(s, LBW_ERR_ARG, "NULL argument");
+    if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
+    if (nsteps < 0) return fail(s, LBW_ERR_ARG, "nsteps must be >= 0");
+    if (((uintptr_t)dev % ALIGN) != 0) return fail(s, LBW_ERR_ARG, "device buffer must be 256-byte aligned");
+    const DevStateLayout d = dev_state_layout(s);
+    if (stride < d.total || stride % ALIGN != 0)
+        return fail(s, LBW_ERR_ARG, "stride must be a multiple of 256 of at least lbw_state_device_bytes()");
+    if (nsteps == 0) return LBW_OK;
+    if (!s->canonical) return fail(s, LBW_ERR_STATE, "state is not canonical");
+    const Ops ops = ops_for(s->g);
+    const size_t nc = (size_t)s->g.nz * s->g.nx;
+    char *base = (char *)dev;
+    for (int m = 0; m < nsteps; ++m) {
+        // the fused launches of lbw_step, reading the previous record (the
+        // first one the canonical state) and writing record m
+        StepArgs a = base_args(s);
+        set_io(s, a);
+        if (m > 0) {
+            const char *in = base + (size_t)(m - 1) * stride;
+            a.src = in + d.pop;
+            a.ez_in = (const double *)(in + d.fld[0]);
+            a.ex_in = (const double *)(in + d.fld[1]);
+            a.by_in = (const double *)(in + d.fld[2]);
+        }
+        char *out = base + (size_t)m * stride;
+        a.dst = out + d.pop;
+        a.ez_out = (double *)(out + d.fld[0]);
+        a.ex_out = (double *)(out + d.fld[1]);
+        a.by_out = (double *)(out + d.fld[2]);
+        a.do_pull = m > 0 ? 1 : 0;
+        a.do_maxwell = m > 0 ? 1 : 0;
+        a.lag_init = s->lag_valid ? 0 : 1;
+        ops.step(a, s->stream);
+        s->lag_valid = true;
+        s->step++;
+    }
+    // canonicalisation of the last record into the simulation's own buffers
+    const char *last = base + (size_t)(nsteps - 1) * stride;
+    StepArgs f = base_args(s);
+    f.src = last + d.pop;
+    f.dst = s->ws + s->L.pop[s->pcur];
+    f.ez_in = (const double *)(last + d.fld[0]);
+    f.ex_in = (const double *)(last + d.fld[1]);
+    f.by_in = (const double *)(last + d.fld[2]);
+    f.ez_out = (double *)(s->ws + s->L.fld[s->fcur][0]);
+    f.ex_out = (double *)(s->ws + s->L.fld[s->fcur][1]);
+    f.by_out = (double *)(s->ws + s->L.fld[s->fcur][2]);
+    double *stage = (double *)(s->ws + s->L.stage);
+    ops.finish(f, stage, stage + nc, s->stream);
+    HIPCHK(s, hipGetLastError());
+    s->canonical = true;
+    return LBW_OK;
+}
+
 lbw_status lbw_load_state_device(lbw_sim *s, const void *dev, long step)
 {
     if (!s || !dev) return fail(s, LBW_ERR_ARG, "NULL argument");
@@ -1328,10 +1384,11 @@ static void slice_window(const AdjArgs &a, double t, double zoff, int &i0, int &
 }
 
 template <class ST>
-static void adj_step_launch(const AdjArgs &a, double *col, hipStream_t st)
+static void adj_step_launch(const AdjArgs &a, double *col, hipStream_t st, bool pulled_n, bool pulled_n1)
 {
     const int nb = (a.ncell + 255) / 256;
-    hipLaunchKernelGGL((k_adj_maxwell<ST>), dim3(nb), dim3(256), 0, st, a);
+    if (pulled_n1) hipLaunchKernelGGL((k_adj_maxwell<ST, true>), dim3(nb), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_adj_maxwell<ST, false>), dim3(nb), dim3(256), 0, st, a);
     // slice derivatives read the adjoint of E^{n+1} before it is overwritten
     const double th = (a.step + 0.5) * a.dt;
     int i0, i1;
@@ -1343,35 +1400,53 @@ static void adj_step_launch(const AdjArgs &a, double *col, hipStream_t st)
                            a.dt);
     }
     hipLaunchKernelGGL(k_adj_stream, dim3(nb), dim3(256), 0, st, a);
-    hipLaunchKernelGGL((k_adj_collide<ST>), dim3(nb), dim3(256), 0, st, a);
+    if (pulled_n) hipLaunchKernelGGL((k_adj_collide<ST, true>), dim3(nb), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_adj_collide<ST, false>), dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_adj_bh, dim3(nb), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_adj_fields, dim3(nb), dim3(256), 0, st, a);
 }
 }  // extern "C++"
 
-lbw_status lbw_adjoint_step(lbw_sim *s, const void *state_n, const void *state_n1, long n, double *adj,
-                            double *grad, void *scratch)
+// One reverse step: pops_n holds state n's populations (canonical, or the
+// post-collision values of step n - 1 when pulled_n), pops_n1 state n + 1's
+// (likewise), fields holds state n's E^n and B^{n-1/2}.
+static lbw_status adjoint_step(lbw_sim *s, const char *pops_n, bool pulled_n, const char *pops_n1, bool pulled_n1,
+                               const char *fields, long n, double *adj, double *grad, void *scratch)
 {
     AdjArgs a;
     lbw_status rc = adj_args(s, adj, grad, scratch, a);
     if (rc != LBW_OK) return rc;
-    if (!state_n || !state_n1) return fail(s, LBW_ERR_ARG, "NULL state");
     if (n < 0) return fail(s, LBW_ERR_ARG, "step must be >= 0");
     const DevStateLayout d = dev_state_layout(s);
-    const char *p0 = (const char *)state_n, *p1 = (const char *)state_n1;
-    a.fn = p0 + d.pop;
-    a.fn1 = p1 + d.pop;
-    a.ez = (const double *)(p0 + d.fld[0]);
-    a.ex = (const double *)(p0 + d.fld[1]);
-    a.by = (const double *)(p0 + d.fld[2]);
+    a.fn = pops_n + d.pop;
+    a.fn1 = pops_n1 + d.pop;
+    a.ez = (const double *)(fields + d.fld[0]);
+    a.ex = (const double *)(fields + d.fld[1]);
+    a.by = (const double *)(fields + d.fld[2]);
     a.step = n;
     double *col = (double *)((char *)scratch + ((size_t)s->L.K * s->L.Q + ADJ_SCRATCH_PLANES) *
                                                    align_up((size_t)a.ncell * 8));
-    if (s->g.storage == LBW_FP64) adj_step_launch<double>(a, col, s->stream);
-    else if (s->g.storage == LBW_FP32) adj_step_launch<float>(a, col, s->stream);
-    else adj_step_launch<__half>(a, col, s->stream);
+    if (s->g.storage == LBW_FP64) adj_step_launch<double>(a, col, s->stream, pulled_n, pulled_n1);
+    else if (s->g.storage == LBW_FP32) adj_step_launch<float>(a, col, s->stream, pulled_n, pulled_n1);
+    else adj_step_launch<__half>(a, col, s->stream, pulled_n, pulled_n1);
     HIPCHK(s, hipGetLastError());
     return LBW_OK;
+}
+
+lbw_status lbw_adjoint_step(lbw_sim *s, const void *state_n, const void *state_n1, long n, double *adj,
+                            double *grad, void *scratch)
+{
+    if (s && (!state_n || !state_n1)) return fail(s, LBW_ERR_ARG, "NULL state");
+    return adjoint_step(s, (const char *)state_n, false, (const char *)state_n1, false, (const char *)state_n, n,
+                        adj, grad, scratch);
+}
+
+lbw_status lbw_adjoint_step_post(lbw_sim *s, const void *pops_n, int pops_n_post, const void *rec_n, long n,
+                                 double *adj, double *grad, void *scratch)
+{
+    if (s && (!pops_n || !rec_n)) return fail(s, LBW_ERR_ARG, "NULL state");
+    return adjoint_step(s, (const char *)pops_n, pops_n_post != 0, (const char *)rec_n, true, (const char *)rec_n,
+                        n, adj, grad, scratch);
 }
 
 lbw_status lbw_adjoint_init_fields(lbw_sim *s, const double *adj, double *grad, void *scratch)

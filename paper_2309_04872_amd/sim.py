@@ -247,6 +247,15 @@ class Sim:
         self._check(self._lib.lbw_step_record(self._h, int(nsteps), p, stride))
         return self
 
+    def step_record_post(self, nsteps, buf, stride=None):
+        """Advance nsteps steps, writing each fused launch's output (the
+        post-collision populations and the fields) into ``buf`` at offsets
+        0, stride, 2 stride, ... (lbw_step_record_post)."""
+        stride = self.state_device_bytes() if stride is None else int(stride)
+        p = self._device_buffer(buf, nsteps * stride, "step_record_post")
+        self._check(self._lib.lbw_step_record_post(self._h, int(nsteps), p, stride))
+        return self
+
     def load_state_device(self, buf, step):
         p = self._device_buffer(buf, self.state_device_bytes(), "load_state_device")
         self._check(self._lib.lbw_load_state_device(self._h, p, int(step)))

@@ -445,6 +445,61 @@ def test_step_record_bitwise(dims, closure, storage, geom):
         a.step_record(2, rec, sb + 8)
 
 
+@pytest.mark.parametrize("dims,closure,storage,geom", [
+    (2, "lec", "fp32", "slab"), (2, "warmc", "fp64", "slab"), (2, "warmc", "fp16dev", "axi"),
+    (2, "lec", "fp16dev", "slab"), (1, "lec", "fp64", "slab")])
+def test_step_record_post_bitwise(dims, closure, storage, geom):
+    """lbw_step_record_post: the final state equals lbw_step(nsteps) bit for
+    bit and stepping on agrees; streaming each record's populations (done by
+    the canonicalisation of a state built from it) gives the next canonical
+    state's populations, and each record's fields are those of lbw_step
+    stopped at that step."""
+    import torch
+
+    from paper_2309_04872_amd.sim import LbwError, Sim
+
+    nz, nx = (600, 1) if dims == 1 else (100, 40)
+    d = 2 * np.pi / (128 if dims == 1 else 32)
+
+    def fresh():
+        s = Sim(dims, nz, nx, delta=d, closure=closure, storage=storage, geom=geom)
+        s.init_plasma(0.03, n=workloads.density_noise((nx, nz), 1e-3, 8))
+        s.init_driver(0.5, 0.7, 0.5, z0=4.0)
+        return s.step(3)
+
+    print("step_record_post", dims, closure, storage, geom, flush=True)
+    a, b = fresh(), fresh()
+    sb = a.state_device_bytes()
+    rec = torch.zeros(6 * sb, dtype=torch.uint8, device="cuda:0")
+    a.step_record_post(6, rec, sb)
+    assert a.step_count == 9
+    ref = torch.zeros(sb, dtype=torch.uint8, device="cuda:0")
+    for m in range(6):
+        b.step(1)
+        b.save_state_device(ref)
+        torch.cuda.synchronize()
+        # b is now at step 4 + m, whose fields record m + 1 holds (the device-state
+        # layout: populations, then E_z, E_x, B_y, each part 256-byte aligned)
+        if m + 1 < 6:
+            pops_bytes = (nz * nx * {"lec": 3 if dims == 2 else 2, "warmc": 8 if dims == 2 else 4}[closure]
+                          * (9 if dims == 2 else 3) * {"fp64": 8, "fp32": 4, "fp16dev": 2}[storage])
+            off = (pops_bytes + 255) // 256 * 256
+            f_ref = ref[off:off + 3 * ((nz * nx * 8 + 255) // 256 * 256)]
+            f_rec = rec[(m + 1) * sb + off:(m + 1) * sb + off + f_ref.numel()]
+            assert torch.equal(f_rec, f_ref), m
+    assert b.step_count == 9
+    for q in ("n", "uz") + (("lambda",) if closure == "warmc" else ()):
+        assert np.array_equal(a.read(q), b.read(q)), q
+    assert np.array_equal(a.field("ez"), b.field("ez"))
+    a.step(5)
+    b.step(5)
+    for q in ("n", "uz"):
+        assert np.array_equal(a.read(q), b.read(q)), q
+    assert np.array_equal(a.field("ex" if dims == 2 else "ez"), b.field("ex" if dims == 2 else "ez"))
+    with pytest.raises(LbwError, match="ARG"):
+        a.step_record_post(2, rec, sb + 8)
+
+
 @pytest.mark.parametrize("bc", ["open", "periodic"])
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 @pytest.mark.parametrize("closure", ["lec", "warmc"])
