@@ -44,6 +44,10 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden visibility; the declarations below are
+ * its exported interface. */
+#pragma GCC visibility push(default)
+
 typedef enum {
     LBW_OK = 0,
     LBW_ERR_ARG = -1,        /* invalid argument or size mismatch */
@@ -460,6 +464,8 @@ lbw_status lbw_stream_copy(void *dst, const void *src, size_t bytes, void *strea
 
 /* Releases the handle; the workspace and stream stay the caller's. */
 void lbw_destroy(lbw_sim *sim);
+
+#pragma GCC visibility pop
 
 #ifdef __cplusplus
 }

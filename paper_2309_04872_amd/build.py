@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "lbwake.hip")
 SRCS = [SRC, os.path.join(HERE, "csrc", "lbw_batch.hip")]
 DEPS = [*SRCS, os.path.join(HERE, "csrc", "lbw_kernels.hpp"), os.path.join(HERE, "csrc", "lbw_device.hpp"),
-        os.path.join(HERE, "csrc", "lbw_adjoint.hpp"),
+        os.path.join(HERE, "csrc", "lbw_adjoint.hpp"), os.path.join(HERE, "csrc", "lbwake.map"),
         os.path.join(ROOT, "include", "lbwake.h")]
 SO = os.path.join(HERE, "liblbwake.so")
 ARCH = os.environ.get("LBW_OFFLOAD_ARCH", "gfx950")
@@ -23,6 +23,10 @@ HIPCC_FLAGS = [
     # packed FP32 instructions stay off (they have given wrong results on this hardware)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-lambda-capture",
+    # only the C ABI of include/lbwake.h is exported (kernel handles included
+    # in the hidden part by the version script)
+    "-fvisibility=hidden",
+    "-Wl,--version-script=" + os.path.join(HERE, "csrc", "lbwake.map"),
 ]
 
 

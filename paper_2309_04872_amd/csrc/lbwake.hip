@@ -486,6 +486,18 @@ static __global__ void k_diag_publish(const double *raw, const unsigned int *fal
 }
 
 // ---------------------------------------------------------------------------
+// Streaming-copy reference: one 16-byte non-temporal load and store per thread.
+// (A sweep of 1, 2, 4 and 8 accesses per thread and 256- to 1024-thread
+// workgroups, with and without the non-temporal hint, found this form the
+// fastest on gfx950.)
+typedef unsigned int lbw_v4u __attribute__((ext_vector_type(4)));
+static __global__ __launch_bounds__(256) void k_stream_copy(const lbw_v4u *__restrict__ src,
+                                                            lbw_v4u *__restrict__ dst, size_t n16)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 extern "C" {
 
 size_t lbw_workspace_bytes(const lbw_grid_desc *grid)
@@ -495,18 +507,6 @@ size_t lbw_workspace_bytes(const lbw_grid_desc *grid)
 }
 
 const char *lbw_version(void) { return "lbwake 0.1 (gfx950)"; }
-
-// Streaming-copy reference: one 16-byte non-temporal load and store per thread.
-// (A sweep of 1, 2, 4 and 8 accesses per thread and 256- to 1024-thread
-// workgroups, with and without the non-temporal hint, found this form the
-// fastest on gfx950.)
-typedef unsigned int lbw_v4u __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void k_stream_copy(const lbw_v4u *__restrict__ src, lbw_v4u *__restrict__ dst,
-                                                     size_t n16)
-{
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
-}
 
 lbw_status lbw_stream_copy(void *dst, const void *src, size_t bytes, void *stream)
 {

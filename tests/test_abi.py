@@ -181,3 +181,17 @@ def test_stream_copy_host_checks(lib):
 def test_diagnostics_every_null_sim(lib):
     assert lib.lbw_set_diagnostics_every(None, 10, None, 4) == -1
     assert lib.lbw_diagnostics_rows(None) == -1
+
+
+def test_exports_only_the_declared_interface(lib):
+    """The library exports the declared C ABI and nothing else (kernel handles
+    and helpers stay local), where nm is available."""
+    import shutil
+    import subprocess
+
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.SO_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    names = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    assert names == set(_declared()), sorted(names ^ set(_declared()))[:10]
