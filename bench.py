@@ -68,10 +68,10 @@ TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake_axi_lec", "fp64"): 1092.0e6,
     ("wake_axi_lec", "fp32"): 539.0e6,
     ("wake_axi_warmc", "fp64"): 3072.7e6,
-    ("wake_axi_warmc", "fp32"): 1600.9e6,
+    ("wake_axi_warmc", "fp32"): 1743.6e6,
     ("wake2d_lec_fp32", "fp16dev"): 169.9e6,
     ("wake_axi_lec", "fp16dev"): 307.8e6,
-    ("wake_axi_warmc", "fp16dev"): 892.3e6,
+    ("wake_axi_warmc", "fp16dev"): 974.9e6,
 }
 
 

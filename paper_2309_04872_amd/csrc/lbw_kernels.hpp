@@ -97,8 +97,17 @@ __device__ __forceinline__ void collide_all(CT (*s)[Lattice<DIM>::Q], const doub
 // STRIP tile-rows, so that the rows a tile shares with the tiles above and
 // below are still in that XCD's L2 when they are read again.
 // NTS: the post-collision populations are stored with the non-temporal hint.
+// Minimum waves per SIMD asked of the compiler: 3 for the axisymmetric warm
+// closure with FP32 / FP16 populations, which would otherwise take 177 VGPRs
+// and 2 waves; at 168 VGPRs with 16-24 B per lane spilled the 3000 x 600 step
+// is faster (FP32 370 -> 357 us, FP16 284 -> 259 us), and its LDS lets three
+// 256-thread workgroups share a compute unit.
+template <int CL, class ST, bool AXI> constexpr int step2d_min_waves()
+{
+    return (AXI && CL == WARMC && !std::is_same<ST, double>::value) ? 3 : 1;
+}
 template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false, int STRIP = 1, bool NTS = false>
-__global__ __launch_bounds__(TZ *TX / CPT) void k_step2d(StepArgs a)
+__global__ __launch_bounds__(TZ *TX / CPT, (step2d_min_waves<CL, ST, AXI>())) void k_step2d(StepArgs a)
 {
     using L = Lattice<2>;
     using CT = typename Store<ST>::ct;
