@@ -62,7 +62,7 @@ def bytes_per_lu(dims, closure, storage):
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake2d_lec_fp32", "fp32"): 301.2e6,
     ("wake2d_lec_fp32", "fp64"): 605.3e6,
-    ("wake2d_warmc", "fp64"): 6710.4e6,
+    ("wake2d_warmc", "fp64"): 6708.4e6,
     ("wake2d_warmc", "fp32"): 3760.9e6,
     ("wake2d_warmc", "fp16dev"): 2081.2e6,
     ("wake_axi_lec", "fp64"): 1092.0e6,
