@@ -267,6 +267,13 @@ lbw_status lbw_get_timing(lbw_sim *sim, double *kernel_ms, long *launches);
 /* Checkpoint: populations, fields, lagged values, step counter. */
 size_t lbw_state_bytes(const lbw_sim *sim);
 lbw_status lbw_save_state(lbw_sim *sim, void *host, size_t bytes);
+/* The same checkpoint without waiting: the header is written at once, the
+ * device parts are copied on the simulation's stream, after the work queued
+ * there and before the work queued later (steps may be queued at once). The
+ * caller synchronises the stream (or an event recorded on it) before reading
+ * the buffer, which must stay valid until then; pinned host memory
+ * (hipHostMalloc, torch pin_memory) lets the copies overlap the steps. */
+lbw_status lbw_save_state_async(lbw_sim *sim, void *host, size_t bytes);
 lbw_status lbw_load_state(lbw_sim *sim, const void *host, size_t bytes);
 
 /* ---------------------------------------------------------------------------

@@ -27,7 +27,7 @@ FIELDS = {"ez": 0, "ex": 1, "by": 2, "wake_x": 3}
 EXPORTS = [
     "lbw_workspace_bytes", "lbw_create", "lbw_init_plasma", "lbw_init_moments", "lbw_init_driver",
     "lbw_set_field", "lbw_step", "lbw_set_nonfinite_check", "lbw_set_diagnostics_every", "lbw_diagnostics_rows", "lbw_read_moment", "lbw_read_moment_device", "lbw_read_field",
-    "lbw_diagnostics", "lbw_diagnostics_static", "lbw_step_count", "lbw_set_timing", "lbw_get_timing", "lbw_state_bytes", "lbw_save_state", "lbw_load_state",
+    "lbw_diagnostics", "lbw_diagnostics_static", "lbw_step_count", "lbw_set_timing", "lbw_get_timing", "lbw_state_bytes", "lbw_save_state", "lbw_save_state_async", "lbw_load_state",
     "lbw_last_error", "lbw_version", "lbw_destroy",
     "lbw_state_device_bytes", "lbw_save_state_device", "lbw_load_state_device", "lbw_step_record",
     "lbw_step_record_post", "lbw_adjoint_step_post",
@@ -137,6 +137,8 @@ def load(path: str | None = None):
     L.lbw_state_bytes.argtypes = [vp]
     L.lbw_save_state.restype = ctypes.c_int
     L.lbw_save_state.argtypes = [vp, vp, ctypes.c_size_t]
+    L.lbw_save_state_async.restype = ctypes.c_int
+    L.lbw_save_state_async.argtypes = [vp, vp, ctypes.c_size_t]
     L.lbw_load_state.restype = ctypes.c_int
     L.lbw_load_state.argtypes = [vp, vp, ctypes.c_size_t]
     L.lbw_last_error.restype = ctypes.c_char_p

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -1084,7 +1085,9 @@ size_t lbw_state_bytes(const lbw_sim *s)
            (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
 }
 
-lbw_status lbw_save_state(lbw_sim *s, void *host, size_t bytes)
+// The header into the host buffer, then the device parts (and the header's
+// fallback count) queued on the simulation's stream.
+static lbw_status enqueue_save(lbw_sim *s, void *host, size_t bytes)
 {
     if (!s || !host) return fail(s, LBW_ERR_ARG, "NULL argument");
     if (!s->initialized) return fail(s, LBW_ERR_STATE, "init_plasma first");
@@ -1094,7 +1097,9 @@ lbw_status lbw_save_state(lbw_sim *s, void *host, size_t bytes)
     std::memcpy(h.magic, "LBWSTAT1", 8);
     h.dims = s->g.dims; h.nz = s->g.nz; h.nx = s->g.nx; h.closure = s->g.closure;
     h.storage = s->g.storage; h.lag_valid = s->lag_valid; h.step = s->step; h.mu = s->mu;
-    HIPCHK(s, hipMemcpyAsync(&h.fallbacks, s->ws + s->L.fallbacks, 4, hipMemcpyDeviceToHost, s->stream));
+    std::memcpy(host, &h, sizeof(h));
+    HIPCHK(s, hipMemcpyAsync((char *)host + offsetof(StateHeader, fallbacks), s->ws + s->L.fallbacks, 4,
+                             hipMemcpyDeviceToHost, s->stream));
     char *p = (char *)host + sizeof(StateHeader);
     const size_t popb = nc * s->L.K * s->L.Q * storage_size(s->g.storage);
     HIPCHK(s, hipMemcpyAsync(p, s->ws + s->L.pop[s->pcur], popb, hipMemcpyDeviceToHost, s->stream));
@@ -1103,10 +1108,18 @@ lbw_status lbw_save_state(lbw_sim *s, void *host, size_t bytes)
         HIPCHK(s, hipMemcpyAsync(p, s->ws + s->L.fld[s->fcur][f], nc * 8, hipMemcpyDeviceToHost, s->stream));
     const size_t lagb = (size_t)nlag(s->g.dims, s->g.closure) * nc * 8;
     if (lagb) HIPCHK(s, hipMemcpyAsync(p, lag_cur(s), lagb, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
-    std::memcpy(host, &h, sizeof(h));
     return LBW_OK;
 }
+
+lbw_status lbw_save_state(lbw_sim *s, void *host, size_t bytes)
+{
+    lbw_status rc = enqueue_save(s, host, bytes);
+    if (rc != LBW_OK) return rc;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return LBW_OK;
+}
+
+lbw_status lbw_save_state_async(lbw_sim *s, void *host, size_t bytes) { return enqueue_save(s, host, bytes); }
 
 lbw_status lbw_load_state(lbw_sim *s, const void *host, size_t bytes)
 {

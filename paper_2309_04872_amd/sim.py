@@ -267,6 +267,22 @@ class Sim:
         self._check(self._lib.lbw_save_state(self._h, ctypes.cast(buf, ctypes.c_void_p), n))
         return buf.raw
 
+    def save_state_async(self, buf):
+        """Queue a checkpoint into ``buf``, a pinned uint8 CPU tensor of
+        lbw_state_bytes() bytes, on the simulation's stream and return at once;
+        synchronise the stream before reading it (bytes(buf.numpy()))."""
+        import torch
+
+        n = self._lib.lbw_state_bytes(self._h)
+        if not isinstance(buf, torch.Tensor) or buf.is_cuda or buf.dtype != torch.uint8 or not buf.is_contiguous():
+            raise ValueError("save_state_async: a contiguous uint8 CPU tensor is required")
+        if not buf.is_pinned():
+            raise ValueError("save_state_async: the tensor must be pinned (pin_memory=True)")
+        if buf.numel() < n:
+            raise ValueError(f"save_state_async: {buf.numel()} bytes, {n} needed")
+        self._check(self._lib.lbw_save_state_async(self._h, ctypes.c_void_p(buf.data_ptr()), n))
+        return buf
+
     def load_state(self, data: bytes):
         buf = ctypes.create_string_buffer(data, len(data))
         self._check(self._lib.lbw_load_state(self._h, ctypes.cast(buf, ctypes.c_void_p), len(data)))

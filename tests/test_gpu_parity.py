@@ -793,3 +793,37 @@ def test_diagnostics_every_argument_checks():
     assert L.lbw_set_diagnostics_every(s._h, 5, None, 4) == -1
     assert L.lbw_set_diagnostics_every(s._h, 0, None, 0) == 0
     s.close()
+
+
+def test_save_state_async_matches_save_state():
+    """A checkpoint queued with lbw_save_state_async and steps queued behind it
+    holds, once the stream is synchronised, the bytes lbw_save_state gives at
+    that step; loading it and stepping on reproduces the run."""
+    import torch
+
+    from paper_2309_04872_amd.sim import Sim
+
+    def fresh():
+        s = Sim(2, 96, 40, delta=2 * np.pi / 32, closure="warmc", storage="fp32")
+        s.init_plasma(0.02, n=workloads.density_noise((40, 96), 1e-2, 12))
+        s.init_driver(0.6, 1.0, 0.5, z0=4.0)
+        return s
+
+    a, b = fresh(), fresh()
+    a.step(9)
+    b.step(9)
+    n = a._lib.lbw_state_bytes(a._h)
+    buf = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    a.save_state_async(buf)
+    a.step(11)
+    a.stream.synchronize()
+    assert bytes(buf.numpy()) == b.save_state()
+    c = fresh()
+    c.load_state(bytes(buf.numpy()))
+    c.step(11)
+    for q in ("n", "uz", "thzz"):
+        assert np.array_equal(c.read(q), a.read(q)), q
+    with pytest.raises(ValueError, match="pinned"):
+        a.save_state_async(torch.empty(n, dtype=torch.uint8))
+    for s in (a, b, c):
+        s.close()
