@@ -299,7 +299,8 @@ lbw_status lbw_load_state_device(lbw_sim *sim, const void *device_src, long step
  * step's closing canonicalisation (streaming and field completion, Sec. 2.1
  * and Sec. 5) writes its record directly and the next step reads it, so no
  * state is copied. For checkpoint-and-recompute. Asynchronous on the stream;
- * not included in lbw_set_timing's kernel timing. */
+ * not included in lbw_set_timing's kernel timing, and without the optional
+ * non-finite checks and diagnostics records of lbw_step. */
 lbw_status lbw_step_record(lbw_sim *sim, int nsteps, void *device_states, size_t stride);
 
 /* The same steps as lbw_step(sim, nsteps) from a canonical state at step n0,
@@ -311,7 +312,8 @@ lbw_status lbw_step_record(lbw_sim *sim, int nsteps, void *device_states, size_t
  * written). Each launch reads the previous record, and only the last is
  * canonicalised, into the simulation, whose final state equals that of
  * lbw_step(sim, nsteps) bit for bit. For the recompute of
- * lbw_adjoint_step_post; asynchronous on the stream. */
+ * lbw_adjoint_step_post; asynchronous on the stream, without lbw_step's
+ * optional non-finite checks, diagnostics records and kernel timing. */
 lbw_status lbw_step_record_post(lbw_sim *sim, int nsteps, void *device_states, size_t stride);
 
 /* ---------------------------------------------------------------------------

@@ -447,7 +447,7 @@ def test_step_record_bitwise(dims, closure, storage, geom):
 
 @pytest.mark.parametrize("dims,closure,storage,geom", [
     (2, "lec", "fp32", "slab"), (2, "warmc", "fp64", "slab"), (2, "warmc", "fp16dev", "axi"),
-    (2, "lec", "fp16dev", "slab"), (1, "lec", "fp64", "slab")])
+    (2, "lec", "fp16dev", "slab"), (1, "lec", "fp64", "slab"), (1, "warmc", "fp32", "slab")])
 def test_step_record_post_bitwise(dims, closure, storage, geom):
     """lbw_step_record_post: the final state equals lbw_step(nsteps) bit for
     bit and stepping on agrees; streaming each record's populations (done by
