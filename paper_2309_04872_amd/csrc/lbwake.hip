@@ -47,10 +47,13 @@ namespace {
 #define LBW_TX2_W 4
 #endif
 #ifndef LBW_TZ2_WF64
-#define LBW_TZ2_WF64 32
+#define LBW_TZ2_WF64 64
 #endif
 #ifndef LBW_TX2_WF64
-#define LBW_TX2_WF64 8
+#define LBW_TX2_WF64 4
+#endif
+#ifndef LBW_STRIP_WF64
+#define LBW_STRIP_WF64 6
 #endif
 #ifndef LBW_TZ2_S
 #define LBW_TZ2_S 64
@@ -82,11 +85,17 @@ template <> struct Tile2<LEC, double> {
 template <class ST> struct Tile2<WARMC, ST> {
     static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1, STRIP = 1;
 };
-// measured 3.6 % faster than 64 x 4 for FP64; strips of 4 tile-rows: 4096 x 1024
-// 1310 -> 1246 us (strips of 1, 2, 4 measured for every 2D case: elsewhere within
-// +-2 % or slower)
+// Warm closure, FP64, slab: 64 x 4 tiles in strips of 6 tile-rows. Swept on
+// 4096 x 1024 (us per step): 32 x 8 in strips of 1, 2, 3, 4, 5, 6, 8, 12, 16:
+// 1310, 1255, 1222, 1255, 1243, 1231, 1333, 1309, 1272; 64 x 4 in strips of 4 to
+// 14, 20, 24, 32: 1258, 1204 (5), 1190 (6), 1242 (7), 1234-1241 (8), 1294 (9),
+// 1214 (10), 1209 (11), 1193-1199 (12), 1246 (13), 1212 (14), 1238, 1276, 1245;
+// 128 x 2 in strips of 8 or 16: 1324. The fused kernel streams its 72 planes at
+// the rate a plain multi-plane copy reaches, so the order that keeps a tile's
+// ring rows and columns in L2 is what is left, and it does not vary smoothly
+// with the strip height.
 template <> struct Tile2<WARMC, double> {
-    static constexpr int TZ = LBW_TZ2_WF64, TX = LBW_TX2_WF64, CPT = 1, STRIP = 4;
+    static constexpr int TZ = LBW_TZ2_WF64, TX = LBW_TX2_WF64, CPT = 1, STRIP = LBW_STRIP_WF64;
 };
 // Warm closure, FP64, axisymmetric geometry: 64 x 4 (the paper's 3000 x 600
 // grid: 573 us per step against 605 us with 32 x 8; both 256 threads and two
@@ -499,6 +508,34 @@ static __global__ __launch_bounds__(256) void k_stream_copy(const lbw_v4u *__res
     if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Multi-plane streaming reference: nplanes planes of nodes elements, one node
+// per thread, every plane loaded before any is stored (the fused step's
+// pattern without its pulls, ring or arithmetic). Moving 72 FP64 planes this
+// way runs at 5.2-5.5 TB/s on gfx950 against 6.1-6.6 TB/s for one contiguous
+// stream; grouping the planes (load and store 1, 4, 9, 18 or 36 at a time),
+// a tile-blocked layout, 16-byte accesses and non-temporal hints did not
+// close the gap. The step's state has this shape, so this is its practical
+// ceiling beside the plain copy's.
+template <int NP, class T>
+static __global__ __launch_bounds__(256) void k_stream_planes(const T *__restrict__ src,
+                                                              T *__restrict__ dst, size_t nodes)
+{
+    const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nodes) return;
+    T v[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) v[p] = src[p * nodes + c];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) dst[p * nodes + c] = v[p];
+}
+
+template <int NP, class T>
+static void launch_stream_planes(const void *src, void *dst, size_t nodes, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_stream_planes<NP, T>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, st,
+                       (const T *)src, (T *)dst, nodes);
+}
+
 extern "C" {
 
 size_t lbw_workspace_bytes(const lbw_grid_desc *grid)
@@ -521,6 +558,35 @@ lbw_status lbw_stream_copy(void *dst, const void *src, size_t bytes, void *strea
     if (blocks > 0xFFFFFFFFull) return LBW_ERR_ARG;
     hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                        (const lbw_v4u *)src, (lbw_v4u *)dst, n16);
+    return hipGetLastError() == hipSuccess ? LBW_OK : LBW_ERR_HIP;
+}
+
+lbw_status lbw_stream_planes(void *dst, const void *src, int nplanes, size_t nodes, int elem_bytes,
+                             void *stream)
+{
+    if (!dst || !src) return LBW_ERR_ARG;
+    if (nplanes != 6 && nplanes != 12 && nplanes != 27 && nplanes != 72) return LBW_ERR_ARG;
+    if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return LBW_ERR_ARG;
+    const uintptr_t d = (uintptr_t)dst, sp = (uintptr_t)src;
+    if ((d | sp) % (uintptr_t)elem_bytes) return LBW_ERR_ARG;
+    if (nodes == 0) return LBW_OK;
+    if ((nodes + 255) / 256 > 0xFFFFFFFFull || nodes > (SIZE_MAX / 2) / ((size_t)nplanes * elem_bytes))
+        return LBW_ERR_ARG;
+    const size_t bytes = (size_t)nplanes * nodes * elem_bytes;
+    if (d < sp + bytes && sp < d + bytes) return LBW_ERR_ARG;
+    const hipStream_t st = (hipStream_t)stream;
+    auto go = [&](auto np) {
+        constexpr int NP = decltype(np)::value;
+        if (elem_bytes == 8) launch_stream_planes<NP, uint64_t>(src, dst, nodes, st);
+        else if (elem_bytes == 4) launch_stream_planes<NP, uint32_t>(src, dst, nodes, st);
+        else launch_stream_planes<NP, uint16_t>(src, dst, nodes, st);
+    };
+    switch (nplanes) {
+    case 6: go(std::integral_constant<int, 6>{}); break;
+    case 12: go(std::integral_constant<int, 12>{}); break;
+    case 27: go(std::integral_constant<int, 27>{}); break;
+    default: go(std::integral_constant<int, 72>{}); break;
+    }
     return hipGetLastError() == hipSuccess ? LBW_OK : LBW_ERR_HIP;
 }
 
