@@ -82,8 +82,12 @@ constexpr size_t MALL_BYTES = size_t(256) << 20;
 template <> struct Tile2<LEC, double> {
     static constexpr int TZ = LBW_TZ2_F64, TX = LBW_TX2_F64, CPT = 1, STRIP = 1;
 };
+// Warm closure, FP32 / FP16-deviation storage: 64 x 4 tiles in strips of 3
+// tile-rows (4096 x 1024: FP32 684.5 -> 669.6 and 686.1 -> 670.9 us, FP16
+// 492.6 -> 484.7 and 493.3 -> 485.4 us on two boxes; axisymmetric 3000 x 600
+// FP32 357.4 -> 352.8 us; strips of 4, 6, 12 measured equal or slower).
 template <class ST> struct Tile2<WARMC, ST> {
-    static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1, STRIP = 1;
+    static constexpr int TZ = LBW_TZ2_W, TX = LBW_TX2_W, CPT = 1, STRIP = 3;
 };
 // Warm closure, FP64, slab: 64 x 4 tiles in strips of 6 tile-rows. Swept on
 // 4096 x 1024 (us per step): 32 x 8 in strips of 1, 2, 3, 4, 5, 6, 8, 12, 16:
@@ -263,18 +267,18 @@ void set_io(lbw_sim *s, StepArgs &a)
 
 // Non-temporal population stores in the 2D fused step, where they measured
 // faster (FP32 warm slab 4096 x 1024: 726 -> 693 us, FP16-deviation 513 ->
-// 493 us; FP32 local equilibrium axisymmetric 3000 x 600: 156 -> 146 us).
-// Elsewhere they measured slower (FP64 warm slab 1254 -> 1350 us, FP16 local
-// equilibrium 48.9 -> 56.0 us, warm axisymmetric FP32 371 -> 377 us and FP16
-// 284 -> 305 us). Only when the two population buffers exceed the
+// 493 us, FP64 on its 64 x 4 tiles in strips of 6: 1198 -> 1166 us; FP32 local
+// equilibrium axisymmetric 3000 x 600: 156 -> 146 us). Elsewhere they measured
+// slower (FP64 warm slab on 32 x 8 tiles in strips of 4 1254 -> 1350 us, FP16
+// local equilibrium 48.9 -> 56.0 us, warm axisymmetric FP32 371 -> 377 us and
+// FP16 284 -> 305 us). Only when the two population buffers exceed the
 // last-level cache: below it the hint sends to HBM what the next kernel would
 // have read from that cache (1024 x 256 FP32 local equilibrium: the
 // canonicalisation after a step 15.6 -> 21.8 us).
 template <int CL, class ST, bool AXI> constexpr bool nt_pop_stores()
 {
     if constexpr (std::is_same<ST, float>::value) return CL == LEC || !AXI;
-    else if constexpr (std::is_same<ST, __half>::value) return CL == WARMC && !AXI;
-    else return false;
+    else return CL == WARMC && !AXI;
 }
 
 template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
