@@ -62,16 +62,16 @@ def bytes_per_lu(dims, closure, storage):
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake2d_lec_fp32", "fp32"): 301.2e6,
     ("wake2d_lec_fp32", "fp64"): 605.3e6,
-    ("wake2d_warmc", "fp64"): 6469.7e6,
-    ("wake2d_warmc", "fp32"): 3360.0e6,
-    ("wake2d_warmc", "fp16dev"): 1869.6e6,
+    ("wake2d_warmc", "fp64"): 6427.6e6,
+    ("wake2d_warmc", "fp32"): 3326.6e6,
+    ("wake2d_warmc", "fp16dev"): 1884.0e6,
     ("wake_axi_lec", "fp64"): 1092.0e6,
     ("wake_axi_lec", "fp32"): 539.0e6,
     ("wake_axi_warmc", "fp64"): 3072.7e6,
     ("wake_axi_warmc", "fp32"): 1579.4e6,
-    ("wake_axi_warmc", "fp16dev"): 871.7e6,
-    ("wake2d_lec_fp32", "fp16dev"): 169.9e6,
-    ("wake_axi_lec", "fp16dev"): 307.8e6,
+    ("wake_axi_warmc", "fp16dev"): 814.6e6,
+    ("wake2d_lec_fp32", "fp16dev"): 170.9e6,
+    ("wake_axi_lec", "fp16dev"): 306.2e6,
 }
 
 

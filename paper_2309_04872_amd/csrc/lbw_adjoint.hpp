@@ -149,7 +149,7 @@ __device__ __forceinline__ void moments3(const void *f, const AdjArgs &a, size_t
     for (int k = 0; k < 3; ++k) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) acc += (double)Store<ST>::ld(src + (size_t)(k * L::Q + q) * nc, (int)c);
+        for (int q = 0; q < L::Q; ++q) acc += (double)Pops<ST, 3, L::Q>::ld(src, k, q, nc, (int)c);
         A[k] = a.aref[k] + acc;
     }
 }
@@ -170,7 +170,7 @@ __device__ __forceinline__ void moments3_pulled(const void *f, const AdjArgs &a,
 #pragma unroll
         for (int q = 0; q < L::Q; ++q) {
             const int c = fix_node(j - L::ex(q), a.nx, a.bcx) * a.nz + fix_node(i - L::ez(q), a.nz, a.bcz);
-            acc += (double)Store<ST>::ld(src + (size_t)(k * L::Q + q) * nc, c);
+            acc += (double)Pops<ST, 3, L::Q>::ld(src, k, q, nc, c);
         }
         A[k] = a.aref[k] + acc;
     }

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace lbw {
 
@@ -86,6 +87,64 @@ template <> struct Store<__half> {
         __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), (unsigned short *)p + i);
     }
     __device__ static float rnd(float v) { return __half2float(__float2half_rn(v)); }
+};
+
+// Layout of the K x Q population planes over nc nodes. FP64 and FP32: plane
+// (k, q) holds node c at element (k Q + q) nc + c. FP16 deviations: scalars
+// 2j and 2j + 1 share one 32-bit word per direction and node, element
+// 2 ((j Q + q) nc + c) + (k & 1), so a pull of direction q brings both with
+// one 32-bit access (16-bit accesses, 64 lanes x 2 bytes, bound the FP16
+// step); an odd last scalar keeps plane-major planes after the pairs. Values
+// and rounding are those of Store<ST>; only the addresses differ.
+template <class ST, int K, int Q> struct Pops {
+    using CT = typename Store<ST>::ct;
+    static constexpr bool PAIRED = std::is_same<ST, __half>::value;
+    static constexpr int KP = PAIRED ? K / 2 * 2 : 0;  // scalars held in pairs
+    // uniform pointer to population (k, q) of node 0, and the element step
+    // from one node to the next
+    template <class P> __device__ static P *plane(P *b, int k, int q, size_t nc)
+    {
+        if (k < KP) return b + (size_t)((k >> 1) * Q + q) * nc * 2 + (k & 1);
+        return b + (size_t)KP * Q * nc + (size_t)((k - KP) * Q + q) * nc;
+    }
+    __device__ static constexpr int step(int k) { return k < KP ? 2 : 1; }
+    __device__ static CT ld(const ST *b, int k, int q, size_t nc, int c)
+    {
+        return Store<ST>::ld(plane(b, k, q, nc), c * step(k));
+    }
+    __device__ static void st(ST *b, int k, int q, size_t nc, int c, CT v)
+    {
+        Store<ST>::st(plane(b, k, q, nc), c * step(k), v);
+    }
+    // every scalar of direction q at node c (v[k] = population k), and back;
+    // NT: stores with the non-temporal hint
+    __device__ static void ld_all(const ST *b, int q, size_t nc, int c, CT *v)
+    {
+#pragma unroll
+        for (int k = 0; k < KP; k += 2) {
+            const unsigned w = ((const unsigned *)plane(b, k, q, nc))[c];
+            v[k] = __half2float(__ushort_as_half((unsigned short)(w & 0xffffu)));
+            v[k + 1] = __half2float(__ushort_as_half((unsigned short)(w >> 16)));
+        }
+#pragma unroll
+        for (int k = KP; k < K; ++k) v[k] = Store<ST>::ld(plane(b, k, q, nc), c);
+    }
+    template <bool NT> __device__ static void st_all(ST *b, int q, size_t nc, int c, const CT *v)
+    {
+#pragma unroll
+        for (int k = 0; k < KP; k += 2) {
+            const unsigned w = (unsigned)__half_as_ushort(__float2half_rn(v[k])) |
+                               ((unsigned)__half_as_ushort(__float2half_rn(v[k + 1])) << 16);
+            unsigned *p = (unsigned *)plane(b, k, q, nc) + c;
+            if constexpr (NT) __builtin_nontemporal_store(w, p);
+            else *p = w;
+        }
+#pragma unroll
+        for (int k = KP; k < K; ++k) {
+            if constexpr (NT) Store<ST>::st_nt(plane(b, k, q, nc), c, v[k]);
+            else Store<ST>::st(plane(b, k, q, nc), c, v[k]);
+        }
+    }
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip. Renumber

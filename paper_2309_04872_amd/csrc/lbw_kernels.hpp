@@ -96,15 +96,18 @@ __device__ __forceinline__ void collide_all(CT (*s)[Lattice<DIM>::Q], const doub
 // STRIP > 1: inside an XCD's band the tiles run z-major through strips of
 // STRIP tile-rows, so that the rows a tile shares with the tiles above and
 // below are still in that XCD's L2 when they are read again.
-// NTS: the post-collision populations are stored with the non-temporal hint.
+// NTS: the post-collision populations are stored with the non-temporal hint,
+// and for the warm closure the fields and lagged values too (warm FP64 slab
+// 4096 x 1024: 1150.5 -> 1142.8 us, FP32 669.4 -> 662.8 us).
 // Minimum waves per SIMD asked of the compiler: 3 for the axisymmetric warm
-// closure with FP32 / FP16 populations, which would otherwise take 177 VGPRs
-// and 2 waves; at 168 VGPRs with 16-24 B per lane spilled the 3000 x 600 step
-// is faster (FP32 370 -> 357 us, FP16 284 -> 259 us), and its LDS lets three
-// 256-thread workgroups share a compute unit.
+// closure with FP32 populations, which would otherwise take 177 VGPRs and 2
+// waves; at 168 VGPRs with 16-24 B per lane spilled the 3000 x 600 step is
+// faster (370 -> 357 us), and its LDS lets three 256-thread workgroups share
+// a compute unit. With FP16 deviations held in scalar pairs the same request
+// spills 26 VGPRs and loses (252 -> 282 us), so that case keeps 2 waves.
 template <int CL, class ST, bool AXI> constexpr int step2d_min_waves()
 {
-    return (AXI && CL == WARMC && !std::is_same<ST, double>::value) ? 3 : 1;
+    return (AXI && CL == WARMC && std::is_same<ST, float>::value) ? 3 : 1;
 }
 template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false, int STRIP = 1, bool NTS = false>
 __global__ __launch_bounds__(TZ *TX / CPT, (step2d_min_waves<CL, ST, AXI>())) void k_step2d(StepArgs a)
@@ -113,6 +116,7 @@ __global__ __launch_bounds__(TZ *TX / CPT, (step2d_min_waves<CL, ST, AXI>())) vo
     using CT = typename Store<ST>::ct;
     constexpr int Q = L::Q;
     constexpr int K = NScal<2, CL>::K;
+    using PopL = Pops<ST, K, Q>;
     constexpr int NT = TZ * TX / CPT;
     constexpr int XS = TX / CPT;             // row stride between a thread's nodes
     constexpr int RZ = TZ + 2, RX = TX + 2;  // recovery region (ring of 1)
@@ -177,18 +181,20 @@ __global__ __launch_bounds__(TZ *TX / CPT, (step2d_min_waves<CL, ST, AXI>())) vo
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int c = xs[L::ex(q) + 1] + zs[L::ez(q) + 1];
+            CT v[K];
             if constexpr (AXI) {
                 const bool m = rf[L::ex(q) + 1];
                 const int qs = m ? L::mx(q) : q;
+                PopL::ld_all(src, qs, nc, c, v);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const CT v = Store<ST>::ld(src + (size_t)(k * Q + qs) * nc, c);
                     // deviation storage: f = s + w A_ref, and w is the same for q and mx(q)
-                    s[k][q] = (odd_in_r<CL>(k) && m) ? (CT)(-v - (CT)(2.0 * L::w(q) * aref[k])) : v;
+                    s[k][q] = (odd_in_r<CL>(k) && m) ? (CT)(-v[k] - (CT)(2.0 * L::w(q) * aref[k])) : v[k];
                 }
             } else {
+                PopL::ld_all(src, q, nc, c, v);
 #pragma unroll
-                for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
+                for (int k = 0; k < K; ++k) s[k][q] = v[k];
             }
         }
     };
@@ -363,9 +369,15 @@ __global__ __launch_bounds__(TZ *TX / CPT, (step2d_min_waves<CL, ST, AXI>())) vo
             const int lx = lxb + r * XS, gx = x0 + lx;
             if (gz < nz && gx < nx) {
                 const size_t c = (size_t)gx * nz + gz;
-                a.ez_out[c] = s_ez[lx + 2][lz + 2];
-                a.ex_out[c] = s_ex[lx + 2][lz + 2];
-                a.by_out[c] = s_by[lx + 2][lz + 2];
+                if constexpr (NTS && CL == WARMC) {
+                    __builtin_nontemporal_store(s_ez[lx + 2][lz + 2], a.ez_out + c);
+                    __builtin_nontemporal_store(s_ex[lx + 2][lz + 2], a.ex_out + c);
+                    __builtin_nontemporal_store(s_by[lx + 2][lz + 2], a.by_out + c);
+                } else {
+                    a.ez_out[c] = s_ez[lx + 2][lz + 2];
+                    a.ex_out[c] = s_ex[lx + 2][lz + 2];
+                    a.by_out[c] = s_by[lx + 2][lz + 2];
+                }
             }
         }
         __syncthreads();
@@ -418,8 +430,12 @@ __global__ __launch_bounds__(TZ *TX / CPT, (step2d_min_waves<CL, ST, AXI>())) vo
                     l00 = lagv[r][0]; l0z = lagv[r][1]; l0x = lagv[r][2];
                     lluz = lagv[r][3]; llux = lagv[r][4];
                 }
-                a.lag[0 * nc + c] = th00; a.lag[1 * nc + c] = th0z; a.lag[2 * nc + c] = th0x;
-                a.lag[3 * nc + c] = luz; a.lag[4 * nc + c] = lux;
+                const double lagn[NLAG2] = {th00, th0z, th0x, luz, lux};
+#pragma unroll
+                for (int g = 0; g < NLAG2; ++g) {
+                    if constexpr (NTS) __builtin_nontemporal_store(lagn[g], a.lag + g * nc + c);
+                    else a.lag[g * nc + c] = lagn[g];
+                }
                 const double idt = 1.0 / dt;
                 const double dt00 = (th00 - l00) * idt, dt0z = (th0z - l0z) * idt;
                 const double dt0x = (th0x - l0x) * idt;
@@ -453,12 +469,12 @@ __global__ __launch_bounds__(TZ *TX / CPT, (step2d_min_waves<CL, ST, AXI>())) vo
             }
             collide_all<2, K, CT>(s[r], A[r], aref, F, vz, vx, a.lam, a.omega, dt);
 #pragma unroll
-            for (int k = 0; k < K; ++k)
+            for (int q = 0; q < Q; ++q) {
+                CT v[K];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    if constexpr (NTS) Store<ST>::st_nt(dst + (size_t)(k * Q + q) * nc, (int)c, s[r][k][q]);
-                    else Store<ST>::st(dst + (size_t)(k * Q + q) * nc, (int)c, s[r][k][q]);
-                }
+                for (int k = 0; k < K; ++k) v[k] = s[r][k][q];
+                PopL::template st_all<NTS>(dst, q, nc, (int)c, v);
+            }
         }
     };
     if (edge)
@@ -477,6 +493,7 @@ __device__ __forceinline__ void step1d_tile(const StepArgs &a, int tile, double 
     using CT = typename Store<ST>::ct;
     constexpr int Q = L::Q;
     constexpr int K = NScal<1, CL>::K;
+    using PopL = Pops<ST, K, Q>;
 
     const int tid = threadIdx.x;
     const int nz = a.nz, bcz = a.bcz;
@@ -494,8 +511,10 @@ __device__ __forceinline__ void step1d_tile(const StepArgs &a, int tile, double 
         for (int q = 0; q < Q; ++q) {
             const int sz = a.do_pull ? gz - L::ez(q) : gz;
             const int c = fix_node(sz, nz, bcz);
+            CT v[K];
+            PopL::ld_all(src, q, nc, c, v);
 #pragma unroll
-            for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
+            for (int k = 0; k < K; ++k) s[k][q] = v[k];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -573,9 +592,12 @@ __device__ __forceinline__ void step1d_tile(const StepArgs &a, int tile, double 
         }
         collide_all<1, K, CT>(s, A, aref, F, uz, 0.0, a.lam, a.omega, dt);
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int q = 0; q < Q; ++q) {
+            CT v[K];
 #pragma unroll
-            for (int q = 0; q < Q; ++q) Store<ST>::st(dst + (size_t)(k * Q + q) * nc, (int)c, s[k][q]);
+            for (int k = 0; k < K; ++k) v[k] = s[k][q];
+            PopL::template st_all<false>(dst, q, nc, (int)c, v);
+        }
     }
     __syncthreads();  // the LDS slots are reused by the next tile or step
 }
@@ -613,6 +635,7 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
     using CT = typename Store<ST>::ct;
     constexpr int Q = L::Q;
     constexpr int K = NScal<1, CL>::K;
+    using PopL = Pops<ST, K, Q>;
     const int tid = threadIdx.x;
     const int nz = a.nz, bcz = a.bcz;
     const size_t nc = (size_t)a.ncell;
@@ -682,8 +705,10 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int c = fix_node(z - L::ez(q), nz, bcz);
+        CT v[K];
+        PopL::ld_all(src, q, nc, c, v);
 #pragma unroll
-        for (int k = 0; k < K; ++k) s[k][q] = Store<ST>::ld(src + (size_t)(k * Q + q) * nc, c);
+        for (int k = 0; k < K; ++k) s[k][q] = v[k];
     }
     double Ez = a.ez_in[z];
     double lg[3] = {0.0, 0.0, 0.0};
@@ -742,9 +767,12 @@ __device__ __forceinline__ void step1d_multi(const StepArgs &a, int tile, double
                         for (int g = 0; g < 3; ++g) a.lag_alt[g * nc + zo] = lg[g];
                     }
 #pragma unroll
-                    for (int k = 0; k < K; ++k)
+                    for (int q = 0; q < Q; ++q) {
+                        CT v[K];
 #pragma unroll
-                        for (int q = 0; q < Q; ++q) Store<ST>::st(dst + (size_t)(k * Q + q) * nc, zo, s[k][q]);
+                        for (int k = 0; k < K; ++k) v[k] = s[k][q];
+                        PopL::template st_all<false>(dst, q, nc, zo, v);
+                    }
                 }
             }
         }
@@ -841,6 +869,7 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
     using L = Lattice<DIM>;
     constexpr int Q = L::Q;
     constexpr int K = NScal<DIM, CL>::K;
+    using PopL = Pops<ST, K, Q>;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.ncell) return;
     const int gz = idx % a.nz, gx = idx / a.nz;
@@ -857,9 +886,9 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
             const bool m = DIM == 2 && a.axi && sx < 0;
             if (m) { sx = -1 - sx; qs = Lattice<2>::mx(q); }
             const int c = fix_node(sx, a.nx, a.bcx) * a.nz + fix_node(sz, a.nz, a.bcz);
-            typename Store<ST>::ct v = Store<ST>::ld(src + (size_t)(k * Q + qs) * nc, c);
+            typename Store<ST>::ct v = PopL::ld(src, k, qs, nc, c);
             if (m && odd_in_r<CL>(k)) v = -v - (typename Store<ST>::ct)(2.0 * L::w(q) * a.aref[k]);
-            Store<ST>::st(dst + (size_t)(k * Q + q) * nc, idx, v);
+            PopL::st(dst, k, q, nc, idx, v);
             acc += v;
         }
         A[k] = a.aref[k] + (double)acc;
@@ -944,6 +973,7 @@ __global__ void k_init_pops(void *dst_, const double *A, const double *uzv, cons
     using L = Lattice<DIM>;
     constexpr int Q = L::Q;
     constexpr int K = NScal<DIM, CL>::K;
+    using PopL = Pops<ST, K, Q>;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= ncell) return;
     ST *dst = (ST *)dst_;
@@ -956,7 +986,7 @@ __global__ void k_init_pops(void *dst_, const double *A, const double *uzv, cons
             const double eu = uz * L::ez(q) + ux * L::ex(q);
             const double P = 3.0 * eu / lam + 4.5 * eu * eu / (lam * lam) - 1.5 * uu / (lam * lam);
             const double w = L::w(q);
-            Store<ST>::st(dst + (size_t)(k * Q + q) * nc, idx,
+            PopL::st(dst, k, q, nc, idx,
                           (typename Store<ST>::ct)(w * (Ak - aref[k]) + w * Ak * P));
         }
     }
@@ -969,6 +999,7 @@ __global__ void k_read_moment(StepArgs a, int which, double *out)
     using L = Lattice<DIM>;
     constexpr int Q = L::Q;
     constexpr int K = NScal<DIM, CL>::K;
+    using PopL = Pops<ST, K, Q>;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.ncell) return;
     const size_t nc = (size_t)a.ncell;
@@ -976,7 +1007,7 @@ __global__ void k_read_moment(StepArgs a, int which, double *out)
     double A[K];
     for (int k = 0; k < K; ++k) {
         typename Store<ST>::ct acc = 0;
-        for (int q = 0; q < Q; ++q) acc += Store<ST>::ld(src + (size_t)(k * Q + q) * nc, idx);
+        for (int q = 0; q < Q; ++q) acc += PopL::ld(src, k, q, nc, idx);
         A[k] = a.aref[k] + (double)acc;
     }
     const double n = A[0];
@@ -1100,6 +1131,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_partial(StepArgs a, doubl
     using L = Lattice<DIM>;
     constexpr int Q = L::Q;
     constexpr int K = NScal<DIM, CL>::K;
+    using PopL = Pops<ST, K, Q>;
     __shared__ double red[NDIAG][DIAG_THREADS / 64];
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     double v[NDIAG] = {0, 0, 0, 0, 0, 0};
@@ -1109,7 +1141,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_partial(StepArgs a, doubl
         double A[K];
         for (int k = 0; k < K; ++k) {
             typename Store<ST>::ct acc = 0;
-            for (int q = 0; q < Q; ++q) acc += Store<ST>::ld(src + (size_t)(k * Q + q) * nc, idx);
+            for (int q = 0; q < Q; ++q) acc += PopL::ld(src, k, q, nc, idx);
             A[k] = a.aref[k] + (double)acc;
         }
         const double n = A[0];
