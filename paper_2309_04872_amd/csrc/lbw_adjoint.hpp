@@ -145,13 +145,17 @@ __device__ __forceinline__ void moments3(const void *f, const AdjArgs &a, size_t
     using L = Lattice<2>;
     const ST *src = (const ST *)f;
     const size_t nc = (size_t)a.ncell;
+    using PopL = Pops<ST, 3, L::Q>;
+    double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        double acc = 0.0;
+    for (int q = 0; q < L::Q; ++q) {
+        typename PopL::CT v[3];
+        PopL::ld_all(src, q, nc, (int)c, v);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) acc += (double)Pops<ST, 3, L::Q>::ld(src, k, q, nc, (int)c);
-        A[k] = a.aref[k] + acc;
+        for (int k = 0; k < 3; ++k) acc[k] += (double)v[k];
     }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) A[k] = a.aref[k] + acc[k];
 }
 
 // The same sums for populations held as the previous step's post-collision
@@ -164,16 +168,18 @@ __device__ __forceinline__ void moments3_pulled(const void *f, const AdjArgs &a,
     using L = Lattice<2>;
     const ST *src = (const ST *)f;
     const size_t nc = (size_t)a.ncell;
+    using PopL = Pops<ST, 3, L::Q>;
+    double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        double acc = 0.0;
+    for (int q = 0; q < L::Q; ++q) {
+        const int c = fix_node(j - L::ex(q), a.nx, a.bcx) * a.nz + fix_node(i - L::ez(q), a.nz, a.bcz);
+        typename PopL::CT v[3];
+        PopL::ld_all(src, q, nc, c, v);
 #pragma unroll
-        for (int q = 0; q < L::Q; ++q) {
-            const int c = fix_node(j - L::ex(q), a.nx, a.bcx) * a.nz + fix_node(i - L::ez(q), a.nz, a.bcz);
-            acc += (double)Pops<ST, 3, L::Q>::ld(src, k, q, nc, c);
-        }
-        A[k] = a.aref[k] + acc;
+        for (int k = 0; k < 3; ++k) acc[k] += (double)v[k];
     }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) A[k] = a.aref[k] + acc[k];
 }
 
 // Moments of the state the pointer holds: canonical (PULLED = false) or the

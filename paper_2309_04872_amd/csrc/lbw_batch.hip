@@ -124,6 +124,20 @@ template <int CL> struct Node1 {
     WarmRec w;
 };
 
+// Store a node's K x 3 populations in the layout of lbw_device.hpp (Pops).
+template <int CL, class N>
+__device__ __forceinline__ void store_node(double *dst, size_t nzp, int z, const N &nd)
+{
+    constexpr int K = NScal<1, CL>::K;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = nd.s[k][q];
+        Pops<double, K, 3>::template st_all<false>(dst, q, nzp, z, v);
+    }
+}
+
 template <int CL>
 __device__ __forceinline__ void pull_node(const BInst &P, const double *src, int gz, bool do_pull,
                                           Node1<CL> &nd)
@@ -134,8 +148,10 @@ __device__ __forceinline__ void pull_node(const BInst &P, const double *src, int
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const int c = fix_node(do_pull ? gz - L::ez(q) : gz, P.nz, P.bc);
+        double v[K];
+        Pops<double, K, 3>::ld_all(src, q, nzp, c, v);
 #pragma unroll
-        for (int k = 0; k < K; ++k) nd.s[k][q] = src[(size_t)(k * 3 + q) * nzp + c];
+        for (int k = 0; k < K; ++k) nd.s[k][q] = v[k];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -254,10 +270,7 @@ __device__ __forceinline__ void step_pass(const BInst &P, const double *src, dou
 #pragma unroll
             for (int g = 0; g < 3; ++g) lag[(size_t)g * nzp + gz] = lnew[g];
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + gz] = v.s[k][q];
+        store_node<CL>(dst, nzp, gz, v);
     }
     __syncthreads();  // the next pass reuses the LDS slots
 }
@@ -376,10 +389,7 @@ __device__ __forceinline__ void step_passs(const BInst &P, const double *src, do
 #pragma unroll
                         for (int g = 0; g < 3; ++g) lag_out[(size_t)g * nzp + zo] = lnew[g];
                     }
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + zo] = v.s[k][q];
+                    store_node<CL>(dst, nzp, zo, v);
                 }
             }
         }
@@ -402,10 +412,7 @@ __device__ __forceinline__ int finish_pass(const BInst &P, const double *src, do
         if (gz >= P.nz) continue;
         Node1<CL> v;
         pull_node<CL>(P, src, gz, true, v);
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) dst[(size_t)(k * 3 + q) * nzp + gz] = v.s[k][q];
+        store_node<CL>(dst, nzp, gz, v);
         double uz;
         if constexpr (CL == LEC) {
             LecRec l;

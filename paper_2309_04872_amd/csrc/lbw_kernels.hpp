@@ -100,14 +100,14 @@ __device__ __forceinline__ void collide_all(CT (*s)[Lattice<DIM>::Q], const doub
 // and for the warm closure the fields and lagged values too (warm FP64 slab
 // 4096 x 1024: 1150.5 -> 1142.8 us, FP32 669.4 -> 662.8 us).
 // Minimum waves per SIMD asked of the compiler: 3 for the axisymmetric warm
-// closure with FP32 populations, which would otherwise take 177 VGPRs and 2
-// waves; at 168 VGPRs with 16-24 B per lane spilled the 3000 x 600 step is
-// faster (370 -> 357 us), and its LDS lets three 256-thread workgroups share
-// a compute unit. With FP16 deviations held in scalar pairs the same request
-// spills 26 VGPRs and loses (252 -> 282 us), so that case keeps 2 waves.
+// closure with FP32 / FP16 populations, which would otherwise take 177-179
+// VGPRs and 2 waves; at 168 VGPRs with a few bytes per lane spilled the
+// 3000 x 600 step is faster (FP32 370 -> 357 us with one population per
+// access, FP16 220.1 -> 213.5 us with the 16-byte groups), and its LDS lets
+// three 256-thread workgroups share a compute unit.
 template <int CL, class ST, bool AXI> constexpr int step2d_min_waves()
 {
-    return (AXI && CL == WARMC && std::is_same<ST, float>::value) ? 3 : 1;
+    return (AXI && CL == WARMC && !std::is_same<ST, double>::value) ? 3 : 1;
 }
 template <int CL, class ST, int TZ, int TX, int CPT, bool AXI = false, int STRIP = 1, bool NTS = false>
 __global__ __launch_bounds__(TZ *TX / CPT, (step2d_min_waves<CL, ST, AXI>())) void k_step2d(StepArgs a)
@@ -859,6 +859,28 @@ __global__ __launch_bounds__(TZ) void k_step1d_persist(StepArgs a, int nsteps)
     }
 }
 
+// Zeroth moments A_k = A_ref_k + sum_q s_{k,q} of the populations a node
+// holds (eq. disc-moments-ade), each sum in the storage's arithmetic type in
+// the order q = 0 .. Q-1.
+template <class PopL, class ST>
+__device__ __forceinline__ void moments_at(const ST *src, size_t nc, int idx, const double *aref, double *A)
+{
+    using CT = typename PopL::CT;
+    constexpr int K = PopL::NK, Q = PopL::NQ;
+    CT acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        CT v[K];
+        PopL::ld_all(src, q, nc, idx, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) A[k] = aref[k] + (double)acc[k];
+}
+
 // ---------------------------------------------------------------------------
 // Finish: bring a mid-step state (f*^{n-1}, E^{n-1}, B^{n-3/2}) to the
 // canonical one (f^n, E^n, B^{n-1/2}). Pass 1 streams f* into the other
@@ -876,23 +898,30 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
     const size_t nc = (size_t)a.ncell;
     const ST *src = (const ST *)a.src;
     ST *dst = (ST *)a.dst;
+    using CT = typename Store<ST>::ct;
     double A[K];
-    for (int k = 0; k < K; ++k) {
-        typename Store<ST>::ct acc = 0;
-        for (int q = 0; q < Q; ++q) {
-            const int sz = gz - L::ez(q);
-            int sx = gx - L::ex(q), qs = q;
-            // axisymmetric: the row below the axis is the mirror image of row 0
-            const bool m = DIM == 2 && a.axi && sx < 0;
-            if (m) { sx = -1 - sx; qs = Lattice<2>::mx(q); }
-            const int c = fix_node(sx, a.nx, a.bcx) * a.nz + fix_node(sz, a.nz, a.bcz);
-            typename Store<ST>::ct v = PopL::ld(src, k, qs, nc, c);
-            if (m && odd_in_r<CL>(k)) v = -v - (typename Store<ST>::ct)(2.0 * L::w(q) * a.aref[k]);
-            PopL::st(dst, k, q, nc, idx, v);
-            acc += v;
+    CT acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int sz = gz - L::ez(q);
+        int sx = gx - L::ex(q), qs = q;
+        // axisymmetric: the row below the axis is the mirror image of row 0
+        const bool m = DIM == 2 && a.axi && sx < 0;
+        if (m) { sx = -1 - sx; qs = Lattice<2>::mx(q); }
+        const int c = fix_node(sx, a.nx, a.bcx) * a.nz + fix_node(sz, a.nz, a.bcz);
+        CT v[K];
+        PopL::ld_all(src, qs, nc, c, v);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (m && odd_in_r<CL>(k)) v[k] = -v[k] - (CT)(2.0 * L::w(q) * a.aref[k]);
+            acc[k] += v[k];
         }
-        A[k] = a.aref[k] + (double)acc;
+        PopL::template st_all<false>(dst, q, nc, idx, v);
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) A[k] = a.aref[k] + (double)acc[k];
     double uz, ux;
     if constexpr (CL == LEC) {
         LecRec r;
@@ -980,15 +1009,18 @@ __global__ void k_init_pops(void *dst_, const double *A, const double *uzv, cons
     const size_t nc = (size_t)ncell;
     const double uz = uzv[idx], ux = DIM == 2 ? uxv[idx] : 0.0;
     const double uu = uz * uz + ux * ux;
-    for (int k = 0; k < K; ++k) {
-        const double Ak = A[(size_t)k * nc + idx];
-        for (int q = 0; q < Q; ++q) {
-            const double eu = uz * L::ez(q) + ux * L::ex(q);
-            const double P = 3.0 * eu / lam + 4.5 * eu * eu / (lam * lam) - 1.5 * uu / (lam * lam);
-            const double w = L::w(q);
-            PopL::st(dst, k, q, nc, idx,
-                          (typename Store<ST>::ct)(w * (Ak - aref[k]) + w * Ak * P));
-        }
+    double Ak[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) Ak[k] = A[(size_t)k * nc + idx];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const double eu = uz * L::ez(q) + ux * L::ex(q);
+        const double P = 3.0 * eu / lam + 4.5 * eu * eu / (lam * lam) - 1.5 * uu / (lam * lam);
+        const double w = L::w(q);
+        typename Store<ST>::ct v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = (typename Store<ST>::ct)(w * (Ak[k] - aref[k]) + w * Ak[k] * P);
+        PopL::template st_all<false>(dst, q, nc, idx, v);
     }
 }
 
@@ -1005,11 +1037,7 @@ __global__ void k_read_moment(StepArgs a, int which, double *out)
     const size_t nc = (size_t)a.ncell;
     const ST *src = (const ST *)a.src;
     double A[K];
-    for (int k = 0; k < K; ++k) {
-        typename Store<ST>::ct acc = 0;
-        for (int q = 0; q < Q; ++q) acc += PopL::ld(src, k, q, nc, idx);
-        A[k] = a.aref[k] + (double)acc;
-    }
+    moments_at<PopL>(src, nc, idx, a.aref, A);
     const double n = A[0];
     double v = 0.0;
     if constexpr (CL == LEC) {
@@ -1139,11 +1167,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_partial(StepArgs a, doubl
         const size_t nc = (size_t)a.ncell;
         const ST *src = (const ST *)a.src;
         double A[K];
-        for (int k = 0; k < K; ++k) {
-            typename Store<ST>::ct acc = 0;
-            for (int q = 0; q < Q; ++q) acc += PopL::ld(src, k, q, nc, idx);
-            A[k] = a.aref[k] + (double)acc;
-        }
+        moments_at<PopL>(src, nc, idx, a.aref, A);
         const double n = A[0];
         double uz, ux;
         if constexpr (CL == LEC) {
