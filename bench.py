@@ -123,40 +123,6 @@ def copy_bandwidth_gbs(stream, nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-def planes_bandwidth_gbs(stream, nplanes, nodes, elem_bytes, reps=10):
-    """The population state's own streaming rate: read + write bytes over the
-    duration of lbw_stream_planes (nplanes planes of nodes elements, every
-    plane of a node loaded before any is stored), HIP events on ``stream``."""
-    import ctypes
-
-    import torch
-
-    from paper_2309_04872_amd import _lib
-
-    L = _lib.load()
-    nbytes = nplanes * nodes * elem_bytes
-    with torch.cuda.stream(stream):
-        x = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
-        y = torch.empty_like(x)
-    args = (ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(x.data_ptr()), nplanes, nodes, elem_bytes,
-            ctypes.c_void_p(stream.cuda_stream))
-    if L.lbw_stream_planes(*args) != 0:
-        raise RuntimeError("lbw_stream_planes failed")
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        L.lbw_stream_planes(*args)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    if not torch.equal(x, y):
-        raise RuntimeError("lbw_stream_planes produced a wrong copy")
-    del x, y
-    torch.cuda.empty_cache()
-    return 2 * nbytes / (ms / 1e3) / 1e9
-
-
 def one_thread(fn, seconds):
     """MLUPS of fn(cells_steps_counter) on one oracle thread."""
     import oracle
@@ -636,8 +602,6 @@ def main():
     s.set_timing(False)
     k_avg_s = k_ms / max(k_n, 1) / 1e3
     copy_gbs = copy_bandwidth_gbs(s.stream)
-    nplanes = ((1 + w["dims"]) if w["closure"] == "lec" else (4 if w["dims"] == 1 else 8)) * (3 if w["dims"] == 1 else 9)
-    planes_gbs = planes_bandwidth_gbs(s.stream, nplanes, cells, {"fp64": 8, "fp32": 4, "fp16dev": 2}[w["storage"]])
     blu = bytes_per_lu(w["dims"], w["closure"], w["storage"])
     achieved = blu * cells / k_avg_s / 1e9
     traffic = TRAFFIC_BYTES_PER_LAUNCH.get((args.workload, w["storage"]))
@@ -668,7 +632,6 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-            "planes_gbs": planes_gbs, "frac_of_planes": achieved / planes_gbs,
             "kernel": "k_step2d" if w["dims"] == 2 else "k_step1d_persist",
             "kernel_avg_us": k_avg_s * 1e6, "bytes_per_lu": blu, "launches": k_n,
         },

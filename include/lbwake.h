@@ -471,22 +471,6 @@ const char *lbw_version(void);
  * before any launch), LBW_ERR_HIP if the launch fails. */
 lbw_status lbw_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 
-/* Measurement aid, not a step of the method: the population state's own
- * streaming pattern. src and dst (device pointers, aligned to elem_bytes, not
- * overlapping) each hold nplanes planes of nodes elements of elem_bytes bytes
- * (plane p at element offset p * nodes); one thread per node loads its
- * element of every plane, then stores them all to dst, in 256-thread
- * workgroups. nplanes is 6, 12, 27 or 72 (the K x Q population planes of the
- * 1D and 2D closures), elem_bytes 2, 4 or 8 (FP16, FP32, FP64 storage). Read
- * plus write bytes over its duration is the rate that many concurrent planes
- * sustain, below a single contiguous copy's; it bounds what the fused step
- * can stream. Asynchronous on stream (a hipStream_t; NULL: the null stream).
- * LBW_ERR_ARG for a NULL pointer, an unsupported plane count or element size,
- * misalignment, overlap or a size whose grid would not fit (checked on the
- * host, before any launch), LBW_ERR_HIP if the launch fails. */
-lbw_status lbw_stream_planes(void *dst, const void *src, int nplanes, size_t nodes, int elem_bytes,
-                             void *stream);
-
 /* Releases the handle; the workspace and stream stay the caller's. */
 void lbw_destroy(lbw_sim *sim);
 

@@ -36,7 +36,7 @@ EXPORTS = [
     "lbw_batch_set_config", "lbw_batch_get_config", "lbw_batch_set_schedule", "lbw_batch_get_schedule",
     "lbw_batch_autotune", "lbw_batch_read",
     "lbw_batch_nonfinite", "lbw_batch_step_count", "lbw_batch_get_timing", "lbw_batch_last_error",
-    "lbw_batch_destroy", "lbw_stream_copy", "lbw_stream_planes",
+    "lbw_batch_destroy", "lbw_stream_copy",
 ]
 BATCH_EZ = 100
 
@@ -201,8 +201,6 @@ def load(path: str | None = None):
     L.lbw_batch_destroy.argtypes = [vp]
     L.lbw_stream_copy.restype = ctypes.c_int
     L.lbw_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
-    L.lbw_stream_planes.restype = ctypes.c_int
-    L.lbw_stream_planes.argtypes = [vp, vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, vp]
     if path is None:
         _LIB = L
     return L

@@ -512,34 +512,6 @@ static __global__ __launch_bounds__(256) void k_stream_copy(const lbw_v4u *__res
     if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
-// Multi-plane streaming reference: nplanes planes of nodes elements, one node
-// per thread, every plane loaded before any is stored (the fused step's
-// pattern without its pulls, ring or arithmetic). Moving 72 FP64 planes this
-// way runs at 5.2-5.5 TB/s on gfx950 against 6.1-6.6 TB/s for one contiguous
-// stream; grouping the planes (load and store 1, 4, 9, 18 or 36 at a time),
-// a tile-blocked layout, 16-byte accesses and non-temporal hints did not
-// close the gap. The step's state has this shape, so this is its practical
-// ceiling beside the plain copy's.
-template <int NP, class T>
-static __global__ __launch_bounds__(256) void k_stream_planes(const T *__restrict__ src,
-                                                              T *__restrict__ dst, size_t nodes)
-{
-    const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= nodes) return;
-    T v[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) v[p] = src[p * nodes + c];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) dst[p * nodes + c] = v[p];
-}
-
-template <int NP, class T>
-static void launch_stream_planes(const void *src, void *dst, size_t nodes, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_stream_planes<NP, T>), dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, st,
-                       (const T *)src, (T *)dst, nodes);
-}
-
 extern "C" {
 
 size_t lbw_workspace_bytes(const lbw_grid_desc *grid)
@@ -562,35 +534,6 @@ lbw_status lbw_stream_copy(void *dst, const void *src, size_t bytes, void *strea
     if (blocks > 0xFFFFFFFFull) return LBW_ERR_ARG;
     hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                        (const lbw_v4u *)src, (lbw_v4u *)dst, n16);
-    return hipGetLastError() == hipSuccess ? LBW_OK : LBW_ERR_HIP;
-}
-
-lbw_status lbw_stream_planes(void *dst, const void *src, int nplanes, size_t nodes, int elem_bytes,
-                             void *stream)
-{
-    if (!dst || !src) return LBW_ERR_ARG;
-    if (nplanes != 6 && nplanes != 12 && nplanes != 27 && nplanes != 72) return LBW_ERR_ARG;
-    if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return LBW_ERR_ARG;
-    const uintptr_t d = (uintptr_t)dst, sp = (uintptr_t)src;
-    if ((d | sp) % (uintptr_t)elem_bytes) return LBW_ERR_ARG;
-    if (nodes == 0) return LBW_OK;
-    if ((nodes + 255) / 256 > 0xFFFFFFFFull || nodes > (SIZE_MAX / 2) / ((size_t)nplanes * elem_bytes))
-        return LBW_ERR_ARG;
-    const size_t bytes = (size_t)nplanes * nodes * elem_bytes;
-    if (d < sp + bytes && sp < d + bytes) return LBW_ERR_ARG;
-    const hipStream_t st = (hipStream_t)stream;
-    auto go = [&](auto np) {
-        constexpr int NP = decltype(np)::value;
-        if (elem_bytes == 8) launch_stream_planes<NP, uint64_t>(src, dst, nodes, st);
-        else if (elem_bytes == 4) launch_stream_planes<NP, uint32_t>(src, dst, nodes, st);
-        else launch_stream_planes<NP, uint16_t>(src, dst, nodes, st);
-    };
-    switch (nplanes) {
-    case 6: go(std::integral_constant<int, 6>{}); break;
-    case 12: go(std::integral_constant<int, 12>{}); break;
-    case 27: go(std::integral_constant<int, 27>{}); break;
-    default: go(std::integral_constant<int, 72>{}); break;
-    }
     return hipGetLastError() == hipSuccess ? LBW_OK : LBW_ERR_HIP;
 }
 

@@ -178,25 +178,6 @@ def test_stream_copy_host_checks(lib):
     assert lib.lbw_stream_copy(vp(b), vp(a), 0, None) == 0
 
 
-def test_stream_planes_host_checks(lib):
-    """lbw_stream_planes refuses, on the host and before any launch, NULL
-    pointers, plane counts and element sizes it has no kernel for,
-    misalignment and overlap; no nodes launches nothing."""
-    vp = ctypes.c_void_p
-    a, b = 1 << 20, 1 << 34  # addresses only; never dereferenced on these paths
-    assert lib.lbw_stream_planes(None, vp(a), 72, 1024, 8, None) == -1
-    assert lib.lbw_stream_planes(vp(b), None, 72, 1024, 8, None) == -1
-    assert lib.lbw_stream_planes(vp(b), vp(a), 9, 1024, 8, None) == -1
-    assert lib.lbw_stream_planes(vp(b), vp(a), 72, 1024, 3, None) == -1
-    assert lib.lbw_stream_planes(vp(b), vp(a), 72, 1024, 16, None) == -1
-    assert lib.lbw_stream_planes(vp(b + 4), vp(a), 72, 1024, 8, None) == -1
-    assert lib.lbw_stream_planes(vp(b), vp(a + 2), 27, 1024, 4, None) == -1
-    assert lib.lbw_stream_planes(vp(a + 8), vp(a), 72, 1024, 8, None) == -1  # overlap
-    assert lib.lbw_stream_planes(vp(a), vp(a + 8), 6, 1024, 8, None) == -1
-    assert lib.lbw_stream_planes(vp(b), vp(a), 72, 1 << 60, 8, None) == -1  # grid too large
-    assert lib.lbw_stream_planes(vp(b), vp(a), 12, 0, 2, None) == 0
-
-
 def test_diagnostics_every_null_sim(lib):
     assert lib.lbw_set_diagnostics_every(None, 10, None, 4) == -1
     assert lib.lbw_diagnostics_rows(None) == -1

@@ -89,34 +89,6 @@ def test_stream_copy_exact():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("nplanes,elem", [(72, 8), (27, 4), (12, 2), (6, 8)])
-def test_stream_planes_exact(nplanes, elem):
-    """The multi-plane streaming reference copies every plane bit for bit
-    (a ragged node count, not a multiple of the 256-thread workgroup) on a
-    side stream and writes nothing past the planes."""
-    import ctypes
-
-    import torch
-
-    from paper_2309_04872_amd import _lib
-
-    L = _lib.load()
-    st = torch.cuda.Stream()
-    nodes = 100003
-    n = nplanes * nodes * elem
-    g = torch.Generator(device="cpu").manual_seed(nplanes)
-    x = torch.randint(0, 256, (n,), dtype=torch.uint8, generator=g).cuda()
-    y = torch.zeros(n + 64, dtype=torch.uint8, device="cuda")
-    torch.cuda.synchronize()
-    rc = L.lbw_stream_planes(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(x.data_ptr()), nplanes, nodes,
-                             elem, ctypes.c_void_p(st.cuda_stream))
-    assert rc == 0
-    st.synchronize()
-    assert torch.equal(y[:n], x)
-    assert int(y[n:].count_nonzero()) == 0
-
-
-@pytest.mark.gpu
 def test_library_loaded_before_torch():
     """A fresh process that loads the library through the binding before it
     imports torch itself still finds the GPU."""
