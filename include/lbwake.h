@@ -264,7 +264,11 @@ long lbw_step_count(const lbw_sim *sim);
 lbw_status lbw_set_timing(lbw_sim *sim, int enable);
 lbw_status lbw_get_timing(lbw_sim *sim, double *kernel_ms, long *launches);
 
-/* Checkpoint: populations, fields, lagged values, step counter. */
+/* Checkpoint: populations, fields, lagged values, step counter. The host
+ * format starts with the tag "LBWSTAT2" (populations in the grouped layout of
+ * this library version); lbw_load_state refuses a buffer with another tag,
+ * a different grid, closure or storage, or fewer than lbw_state_bytes bytes
+ * (LBW_ERR_ARG). */
 size_t lbw_state_bytes(const lbw_sim *sim);
 lbw_status lbw_save_state(lbw_sim *sim, void *host, size_t bytes);
 /* The same checkpoint without waiting: the header is written at once, the

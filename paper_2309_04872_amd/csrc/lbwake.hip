@@ -520,7 +520,7 @@ size_t lbw_workspace_bytes(const lbw_grid_desc *grid)
     return make_layout(grid).total;
 }
 
-const char *lbw_version(void) { return "lbwake 0.1 (gfx950)"; }
+const char *lbw_version(void) { return "lbwake 0.2 (gfx950)"; }
 
 lbw_status lbw_stream_copy(void *dst, const void *src, size_t bytes, void *stream)
 {
@@ -1107,7 +1107,7 @@ static lbw_status enqueue_save(lbw_sim *s, void *host, size_t bytes)
     if (bytes < lbw_state_bytes(s)) return fail(s, LBW_ERR_ARG, "buffer too small");
     const size_t nc = (size_t)s->g.nz * s->g.nx;
     StateHeader h{};
-    std::memcpy(h.magic, "LBWSTAT1", 8);
+    std::memcpy(h.magic, "LBWSTAT2", 8);
     h.dims = s->g.dims; h.nz = s->g.nz; h.nx = s->g.nx; h.closure = s->g.closure;
     h.storage = s->g.storage; h.lag_valid = s->lag_valid; h.step = s->step; h.mu = s->mu;
     std::memcpy(host, &h, sizeof(h));
@@ -1140,7 +1140,7 @@ lbw_status lbw_load_state(lbw_sim *s, const void *host, size_t bytes)
     if (bytes < lbw_state_bytes(s)) return fail(s, LBW_ERR_ARG, "buffer too small");
     StateHeader h;
     std::memcpy(&h, host, sizeof(h));
-    if (std::memcmp(h.magic, "LBWSTAT1", 8) != 0 || h.dims != s->g.dims || h.nz != s->g.nz ||
+    if (std::memcmp(h.magic, "LBWSTAT2", 8) != 0 || h.dims != s->g.dims || h.nz != s->g.nz ||
         h.nx != s->g.nx || h.closure != s->g.closure || h.storage != s->g.storage)
         return fail(s, LBW_ERR_ARG, "state does not match this grid");
     const size_t nc = (size_t)s->g.nz * s->g.nx;
