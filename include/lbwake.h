@@ -285,7 +285,13 @@ lbw_status lbw_load_state(lbw_sim *sim, const void *host, size_t bytes);
  * warm closure's lagged values) for checkpoint-and-recompute. The buffer is
  * caller-owned device memory, 256-byte aligned, of lbw_state_device_bytes();
  * layout: the populations (storage type), then E_z, E_x, B_y (FP64), then the
- * lagged values, each part starting on a 256-byte boundary. Both calls are
+ * lagged values, each part starting on a 256-byte boundary. The populations
+ * are those of the library's buffers: over nc = nz nx nodes (node j nz + z),
+ * the K scalars in groups of G that fill 16 bytes (G = 2 for FP64, 4 for
+ * FP32, 8 for FP16, a power of two no larger than K), population (k, q) of
+ * node c at element ((k / G) Q + q) nc G + c G + k % G for k < K - K % G,
+ * and a leftover scalar (k >= K - K % G) at (K - K % G) Q nc
+ * + ((k - K + K % G) Q + q) nc + c. Both calls are
  * asynchronous on the simulation's stream. lbw_load_state_device restores a
  * state saved from a simulation with the same descriptor and plasma (it
  * keeps the current mu, storage reference and driver) and sets the step
