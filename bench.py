@@ -61,17 +61,17 @@ def bytes_per_lu(dims, closure, storage):
 # MALL. Valid for the kernel as profiled; remove an entry when it changes.
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("wake2d_lec_fp32", "fp32"): 299.8e6,
-    ("wake2d_lec_fp32", "fp64"): 604.2e6,
+    ("wake2d_lec_fp32", "fp64"): 576.0e6,
     ("wake2d_lec_fp32", "fp16dev"): 170.6e6,
     ("wake2d_warmc", "fp64"): 6213.3e6,
     ("wake2d_warmc", "fp32"): 3321.5e6,
     ("wake2d_warmc", "fp16dev"): 1883.0e6,
-    ("wake_axi_lec", "fp64"): 1083.9e6,
+    ("wake_axi_lec", "fp64"): 1051.7e6,
     ("wake_axi_lec", "fp32"): 531.5e6,
     ("wake_axi_lec", "fp16dev"): 306.3e6,
-    ("wake_axi_warmc", "fp64"): 3001.2e6,
-    ("wake_axi_warmc", "fp32"): 1539.7e6,
-    ("wake_axi_warmc", "fp16dev"): 913.6e6,
+    ("wake_axi_warmc", "fp64"): 2961.2e6,
+    ("wake_axi_warmc", "fp32"): 1479.9e6,
+    ("wake_axi_warmc", "fp16dev"): 899.8e6,
 }
 
 

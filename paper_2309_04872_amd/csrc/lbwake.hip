@@ -265,21 +265,19 @@ void set_io(lbw_sim *s, StepArgs &a)
     a.by_out = (double *)(s->ws + s->L.fld[1 - s->fcur][2]);
 }
 
-// Non-temporal population stores in the 2D fused step, where they measured
-// faster (FP32 warm slab 4096 x 1024: 726 -> 693 us, FP16-deviation 513 ->
-// 493 us, FP64 on its 64 x 4 tiles in strips of 6: 1198 -> 1166 us; FP32 local
-// equilibrium axisymmetric 3000 x 600: 156 -> 146 us). Elsewhere they measured
-// slower (FP64 warm slab on 32 x 8 tiles in strips of 4 1254 -> 1350 us, FP16
-// local equilibrium 48.9 -> 56.0 us, warm axisymmetric FP32 371 -> 377 us and
-// FP16 284 -> 305 us). Only when the two population buffers exceed the
-// last-level cache: below it the hint sends to HBM what the next kernel would
-// have read from that cache (1024 x 256 FP32 local equilibrium: the
-// canonicalisation after a step 15.6 -> 21.8 us).
-template <int CL, class ST, bool AXI> constexpr bool nt_pop_stores()
-{
-    if constexpr (std::is_same<ST, float>::value) return CL == LEC || !AXI;
-    else return CL == WARMC && !AXI;
-}
+// Non-temporal population stores in the 2D fused step (and, for the warm
+// closure, field and lagged-value stores), whenever the two population
+// buffers exceed the 256 MB last-level cache: below it the hint would send to
+// HBM what the next kernel reads from that cache (1024 x 256 FP32 local
+// equilibrium: the canonicalisation after a step 15.6 -> 21.8 us). Above it
+// they measured faster in every case on the grouped population layout
+// (4096 x 1024 warm FP64 1198 -> 1166 us, FP32 726 -> 693, FP16 513 -> 493
+// before the layout; after it, 2048 x 512 local equilibrium FP64
+// 121.4 -> 107.2 us, the axisymmetric 3000 x 600 local equilibrium FP64
+// 217.5 -> 210.0, warm FP64 542.8 -> 508.4, FP32 297.1 -> 280.9, FP16
+// 213.9 -> 208.5 us). With one population per access some cases had measured
+// slower (warm FP64 on 32 x 8 tiles 1254 -> 1350 us, axisymmetric warm FP32
+// 371 -> 377 and FP16 284 -> 305 us).
 
 template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
     template <class T> static void launch2d(const StepArgs &a, hipStream_t st)
@@ -288,12 +286,10 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
         dim3 grid(((a.nz + T::TZ - 1) / T::TZ) * ((a.nx + T::TX - 1) / T::TX));
         constexpr int K = NScal<2, CL>::K;
         const size_t pop_bytes = (size_t)a.ncell * 2 * K * 9 * sizeof(ST);
-        if constexpr (nt_pop_stores<CL, ST, AXI>()) {
-            if (pop_bytes > MALL_BYTES) {
-                hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP, true>), grid,
-                                   dim3(T::TZ * T::TX / T::CPT), 0, st, a);
-                return;
-            }
+        if (pop_bytes > MALL_BYTES) {
+            hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP, true>), grid,
+                               dim3(T::TZ * T::TX / T::CPT), 0, st, a);
+            return;
         }
         hipLaunchKernelGGL((k_step2d<CL, ST, T::TZ, T::TX, T::CPT, AXI, T::STRIP, false>), grid,
                            dim3(T::TZ * T::TX / T::CPT), 0, st, a);
