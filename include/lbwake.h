@@ -287,8 +287,9 @@ lbw_status lbw_load_state(lbw_sim *sim, const void *host, size_t bytes);
  * layout: the populations (storage type), then E_z, E_x, B_y (FP64), then the
  * lagged values, each part starting on a 256-byte boundary. The populations
  * are those of the library's buffers: over nc = nz nx nodes (node j nz + z),
- * the K scalars in groups of G that fill 16 bytes (G = 2 for FP64, 4 for
- * FP32, 8 for FP16, a power of two no larger than K), population (k, q) of
+ * the K scalars in groups of G, the largest power of two that neither
+ * exceeds K nor makes a group longer than 16 bytes (FP64 2; FP32 4, or 2 for
+ * K = 3; FP16 8 for K = 8, 4 for K = 4, 2 for K = 2 or 3), population (k, q) of
  * node c at element ((k / G) Q + q) nc G + c G + k % G for k < K - K % G,
  * and a leftover scalar (k >= K - K % G) at (K - K % G) Q nc
  * + ((k - K + K % G) Q + q) nc + c. Both calls are
