@@ -335,8 +335,9 @@ lbw_status lbw_step_record_post(lbw_sim *sim, int nsteps, void *device_states, s
  * (the adjoint itself is FP64), any slice count lbw_init_driver accepts; LBW_ERR_UNSUPPORTED
  * otherwise, LBW_ERR_STATE when the driver has no slices.
  *
- * adj (device, FP64, caller-owned) holds the adjoint of a canonical state:
- * K*Q population planes in the population order, then E_z, E_x, B_y, each
+ * adj (device, FP64, caller-owned, 16-byte aligned) holds the adjoint of a
+ * canonical state: its K*Q*nx*nz populations in the layout of the FP64
+ * population buffers (the device checkpoints above), then E_z, E_x, B_y, each
  * nx*nz values; lbw_adjoint_bytes() bytes. scratch: lbw_adjoint_workspace_bytes()
  * bytes of device memory, 256-byte aligned. grad: nslices FP64 values on the
  * device, accumulated into (the caller zeroes it).

@@ -217,9 +217,32 @@ __device__ __forceinline__ NodeF node_fields_at(const AdjArgs &a, int j, int i)
     return f;
 }
 
+// The three FP64 adjoint populations of direction q at node c (the adjoint
+// state and the scratch of the stream kernel), in the layout of the FP64
+// population buffers (Pops: scalars 0 and 1 as one 16-byte pair per
+// direction and node, scalar 2 in planes of its own after the pairs).
+__device__ __forceinline__ void adj_pops_ld(const double *b, int q, size_t nc, size_t c, double *v)
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 w = ((const d2 *)(b + (size_t)q * nc * 2))[c];
+    v[0] = w.x;
+    v[1] = w.y;
+    v[2] = b[(size_t)(18 + q) * nc + c];
+}
+__device__ __forceinline__ void adj_pops_st(double *b, int q, size_t nc, size_t c, const double *v)
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 w;
+    w.x = v[0];
+    w.y = v[1];
+    ((d2 *)(b + (size_t)q * nc * 2))[c] = w;
+    b[(size_t)(18 + q) * nc + c] = v[2];
+}
+
 // (a) Reverse of S9 and S8 at every slot/node y: adjoint of B', the currents'
 // adjoint m'b, through the recovery at n+1 into the adjoint of A' (every
 // population of the node gets it; the stream gather adds it).
+
 // PULLED: fn1 holds the post-collision populations of step n (f*^n).
 template <class ST, bool PULLED>
 __global__ __launch_bounds__(256) void k_adj_maxwell(AdjArgs a)
@@ -272,19 +295,18 @@ __global__ __launch_bounds__(256) void k_adj_stream(AdjArgs a)
         int cx[3], cz[3];
         const int nxc = pre1(jy, -L::ex(q), a.nx, a.bcx, false, cx);
         const int nzc = pre1(iy, -L::ez(q), a.nz, a.bcz, false, cz);
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int u = 0; u < nxc; ++u)
+            for (int v = 0; v < nzc; ++v) {
+                const size_t c = (size_t)cx[u] * a.nz + cz[v];
+                double l[3];
+                adj_pops_ld(a.lf, q, nc, c, l);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double *lfq = a.lf + (size_t)(k * 9 + q) * nc;
-            const double *abk = a.s_ab + (size_t)k * nc;
-            double acc = 0.0;
-            for (int u = 0; u < nxc; ++u)
-                for (int v = 0; v < nzc; ++v) {
-                    const size_t c = (size_t)cx[u] * a.nz + cz[v];
-                    acc += lfq[c] + abk[c];
-                }
-            a.s_fs[(size_t)(k * 9 + q) * nc + y] = acc;
-            Fb[k] += L::w(q) * acc;
-        }
+                for (int k = 0; k < 3; ++k) acc[k] += l[k] + a.s_ab[(size_t)k * nc + c];
+            }
+        adj_pops_st(a.s_fs, q, nc, (size_t)y, acc);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Fb[k] += L::w(q) * acc[k];
     }
     a.s_fz[y] = a.dt * Fb[1];
     a.s_fx[y] = a.dt * Fb[2];
@@ -318,9 +340,12 @@ __global__ __launch_bounds__(256) void k_adj_collide(AdjArgs a)
     // read; one read: 134 -> 122 us per reverse step)
     double fsr[3][9];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int q = 0; q < 9; ++q) {
+        double l[3];
+        adj_pops_ld(a.s_fs, q, nc, (size_t)y, l);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) fsr[k][q] = a.s_fs[(size_t)(k * 9 + q) * nc + y];
+        for (int k = 0; k < 3; ++k) fsr[k][q] = l[k];
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         double sa = 0.0, sz = 0.0, sx = 0.0;
@@ -356,12 +381,15 @@ __global__ __launch_bounds__(256) void k_adj_collide(AdjArgs a)
     double Rb[3];
     lec_recover_adj(J, uzb, uxb, phib, nb, 1.0 + a.two_over_d, Rb);
     const double keep = 1.0 - om;
+    double tot[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double tot = Ab[k] + Rb[k];
+    for (int k = 0; k < 3; ++k) tot[k] = Ab[k] + Rb[k];
 #pragma unroll
-        for (int q = 0; q < 9; ++q)
-            a.lf[(size_t)(k * 9 + q) * nc + y] = keep * fsr[k][q] + tot;
+    for (int q = 0; q < 9; ++q) {
+        double l[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) l[k] = keep * fsr[k][q] + tot[k];
+        adj_pops_st(a.lf, q, nc, (size_t)y, l);
     }
 }
 

@@ -1366,6 +1366,7 @@ static lbw_status adj_args(lbw_sim *s, double *adj, double *grad, void *scratch,
         return fail(s, LBW_ERR_UNSUPPORTED, "the adjoint covers the 2D local-equilibrium closure in slab geometry");
     if (s->drv.nslices <= 0) return fail(s, LBW_ERR_STATE, "the driver has no slices to differentiate");
     if (((uintptr_t)scratch % ALIGN) != 0) return fail(s, LBW_ERR_ARG, "scratch must be 256-byte aligned");
+    if (((uintptr_t)adj % 16) != 0) return fail(s, LBW_ERR_ARG, "adj must be 16-byte aligned");
     const size_t nc = (size_t)s->g.nz * s->g.nx;
     a = AdjArgs{};
     a.lf = adj;
