@@ -884,8 +884,9 @@ __device__ __forceinline__ void moments_at(const ST *src, size_t nc, int idx, co
 // ---------------------------------------------------------------------------
 // Finish: bring a mid-step state (f*^{n-1}, E^{n-1}, B^{n-3/2}) to the
 // canonical one (f^n, E^n, B^{n-1/2}). Pass 1 streams f* into the other
-// buffer and records J^n = -n^n u^n; in 1D it also finishes E_z.
-template <int DIM, int CL, class ST>
+// buffer and records J^n = -n^n u^n; in 1D it also finishes E_z. NT: the
+// populations are stored with the non-temporal hint.
+template <int DIM, int CL, class ST, bool NT = false>
 __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
 {
     using L = Lattice<DIM>;
@@ -918,7 +919,7 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
             if (m && odd_in_r<CL>(k)) v[k] = -v[k] - (CT)(2.0 * L::w(q) * a.aref[k]);
             acc[k] += v[k];
         }
-        PopL::template st_all<false>(dst, q, nc, idx, v);
+        PopL::template st_all<NT>(dst, q, nc, idx, v);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) A[k] = a.aref[k] + (double)acc[k];

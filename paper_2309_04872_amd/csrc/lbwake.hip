@@ -369,7 +369,13 @@ template <int DIM, int CL, class ST, bool AXI = false> struct Impl {
     static void finish(const StepArgs &a, double *jz, double *jx, hipStream_t st)
     {
         const int nb = (a.ncell + 255) / 256;
-        hipLaunchKernelGGL((k_finish_pull<DIM, CL, ST>), dim3(nb), dim3(256), 0, st, a, jz, jx);
+        // non-temporal population stores when the buffers exceed the last-level
+        // cache, as in the fused step
+        constexpr int K = NScal<DIM, CL>::K;
+        if ((size_t)a.ncell * 2 * K * Lattice<DIM>::Q * sizeof(ST) > MALL_BYTES)
+            hipLaunchKernelGGL((k_finish_pull<DIM, CL, ST, true>), dim3(nb), dim3(256), 0, st, a, jz, jx);
+        else
+            hipLaunchKernelGGL((k_finish_pull<DIM, CL, ST, false>), dim3(nb), dim3(256), 0, st, a, jz, jx);
         if constexpr (DIM == 2) {
             hipLaunchKernelGGL(k_finish_b2d, dim3(nb), dim3(256), 0, st, a);
             hipLaunchKernelGGL(k_finish_e2d, dim3(nb), dim3(256), 0, st, a, (const double *)jz,
