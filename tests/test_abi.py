@@ -195,3 +195,27 @@ def test_exports_only_the_declared_interface(lib):
                          check=True).stdout
     names = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
     assert names == set(_declared()), sorted(names ^ set(_declared()))[:10]
+
+
+def test_binding_refuses_host_buffers_for_device_calls():
+    """The binding's device-buffer calls (load_state_device, save_state_device,
+    step_record, step_record_post) hand a raw pointer to the C side, which reads
+    or writes lbw_state_device_bytes() bytes there: anything but a tensor on the
+    simulation's device is refused before the call, and a checkpoint into host
+    memory needs a pinned uint8 tensor of lbw_state_bytes() bytes."""
+    import types
+
+    import torch
+
+    from paper_2309_04872_amd.sim import Sim
+
+    fake = types.SimpleNamespace(device=torch.device("cuda", 0), _h=None,
+                                 _lib=types.SimpleNamespace(lbw_state_bytes=lambda h: 4096))
+    for bad in (torch.zeros(4096, dtype=torch.uint8), bytearray(4096), None):
+        with pytest.raises(ValueError, match="tensor on cuda:0"):
+            Sim._device_buffer(fake, bad, 4096, "load_state_device")
+    with pytest.raises(ValueError, match="pinned"):
+        Sim.save_state_async(fake, torch.zeros(4096, dtype=torch.uint8))
+    for bad in (torch.zeros(4096, dtype=torch.float32), torch.zeros(8192, dtype=torch.uint8)[::2]):
+        with pytest.raises(ValueError, match="contiguous uint8 CPU tensor"):
+            Sim.save_state_async(fake, bad)

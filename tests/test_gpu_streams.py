@@ -105,3 +105,37 @@ def test_library_loaded_before_torch():
             "print('ok')\n")
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
+
+
+def test_device_buffer_refusals_leave_state_unchanged():
+    """load_state_device / save_state_device / step_record refuse a device
+    tensor that is too small, not contiguous or not 256-byte aligned with
+    ValueError before any call reaches the C side; the simulation then steps
+    on exactly as one that never saw the refused calls."""
+    import torch
+
+    ref = _sim()
+    ref.step(10)
+    a = _sim()
+    a.step(10)
+    n = a.state_device_bytes()
+    ok = a.save_state_device()
+    small = torch.zeros(n - 256, dtype=torch.uint8, device=a.device)
+    strided = torch.zeros(2 * n, dtype=torch.uint8, device=a.device)[::2]
+    shifted = torch.zeros(n + 256, dtype=torch.uint8, device=a.device)[1:n + 1]
+    for buf, msg in ((small, "needed"), (strided, "contiguous"), (shifted, "aligned")):
+        with pytest.raises(ValueError, match=msg):
+            a.load_state_device(buf, 10)
+        with pytest.raises(ValueError, match=msg):
+            a.save_state_device(out=buf)
+        with pytest.raises(ValueError, match=msg):
+            a.step_record(1, buf)
+    with pytest.raises(ValueError, match="tensor on"):
+        a.load_state_device(ok.cpu(), 10)
+    torch.cuda.synchronize()
+    assert a.step_count == 10
+    a.step(5)
+    ref.step(5)
+    for q in ("n", "uz", "ux"):
+        np.testing.assert_array_equal(a.read(q), ref.read(q))
+    np.testing.assert_array_equal(a.field("ez"), ref.field("ez"))
