@@ -907,7 +907,11 @@ __device__ __forceinline__ void moments_at(const ST *src, size_t nc, int idx, co
 // Finish: bring a mid-step state (f*^{n-1}, E^{n-1}, B^{n-3/2}) to the
 // canonical one (f^n, E^n, B^{n-1/2}). Pass 1 streams f* into the other
 // buffer and records J^n = -n^n u^n; in 1D it also finishes E_z. NT: the
-// populations are stored with the non-temporal hint.
+// populations are stored with the non-temporal hint. On the 2D slab the
+// workgroups are renumbered into XCD bands, so that row segments whose pulls
+// share cache lines run on one L2 (4096 x 1024 warm FP32 533 -> 462 us, FP64
+// 972 -> 949 us); the axisymmetric grid keeps the dispatch order, which
+// measured faster there (421 against 434 us on 3000 x 600 warm FP64).
 template <int DIM, int CL, class ST, bool NT = false>
 __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
 {
@@ -915,7 +919,8 @@ __global__ void k_finish_pull(StepArgs a, double *jz, double *jx)
     constexpr int Q = L::Q;
     constexpr int K = NScal<DIM, CL>::K;
     using PopL = Pops<ST, K, Q>;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int blk = (DIM == 2 && !a.axi) ? xcd_band_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int idx = blk * blockDim.x + threadIdx.x;
     if (idx >= a.ncell) return;
     const int gz = idx % a.nz, gx = idx / a.nz;
     const size_t nc = (size_t)a.ncell;
